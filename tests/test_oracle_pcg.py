@@ -1,0 +1,88 @@
+"""Pins of the oracle PCG (Algorithm 1): identity preconditioner equals plain
+CG, grid-independent iteration counts, null-space handling and the stop
+rule."""
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import problems
+from oracle import discretize as D
+from oracle import krylov as K
+from oracle import octree as O
+
+from oracle_fixtures import disc_for, half_tree, hierarchy
+
+
+def test_identity_preconditioner_is_plain_cg():
+    """Section 2.2: Precond = I reduces PCG to CG; compared with SciPy's CG
+    after the same number of steps."""
+    d = disc_for(O.Octree(problems.uniform_spec(4)), seed=21)
+    b = np.random.default_rng(22).uniform(-1, 1, d.tree.n)
+    for k in (1, 3, 7):
+        x, info = K.pcg(d.A, b, None, rtol=0.0, max_iter=k)
+        ref = K.cg_textbook_reference(d.A, b, k)
+        assert np.linalg.norm(x - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_grid_independent_iterations_uniform():
+    its = []
+    for l in (4, 5, 6):
+        d = disc_for(O.Octree(problems.uniform_spec(l)))
+        rhs = problems.rhs_manufactured(1, d.tree.level, d.tree.ijk)
+        _, info = K.pcg(d.A, rhs, hierarchy(d).vcycle, 1e-10, 100)
+        its.append(info["iters"])
+    assert max(its) - min(its) <= 2, its
+
+
+def test_grid_independent_iterations_adaptive():
+    its = []
+    for l in (3, 4, 5):
+        d = disc_for(half_tree(l), seed=23)
+        rhs = np.random.default_rng(24).uniform(-1, 1, d.tree.n) * 2.0 ** (-3 * d.tree.level)
+        _, info = K.pcg(d.A, rhs, hierarchy(d).vcycle, 1e-10, 100)
+        its.append(info["iters"])
+    assert max(its) - min(its) <= 3, its
+
+
+def test_null_space_all_neumann():
+    """All-Neumann: the residual is shifted to zero mean (Section 2.2); the
+    result agrees with a direct solve of the system with the mean fixed."""
+    d = disc_for(half_tree(3), bc=(D.NEUMANN,) * 6, seed=25)
+    n = d.tree.n
+    rng = np.random.default_rng(26)
+    b = rng.uniform(-1, 1, n)
+    b -= b.mean()
+    x, info = K.pcg(d.A, b, hierarchy(d).vcycle, 1e-12, 200, null_space=True)
+    assert info["status"] == 0
+    # bordered direct solve: [A 1; 1^T 0] [x; c] = [b; 0]
+    A = d.A.toarray()
+    Bm = np.zeros((n + 1, n + 1))
+    Bm[:n, :n] = A
+    Bm[:n, n] = 1.0
+    Bm[n, :n] = 1.0
+    ref = np.linalg.solve(Bm, np.concatenate([b, [0.0]]))[:n]
+    assert np.linalg.norm(x - ref) <= 1e-9 * np.linalg.norm(ref)
+    assert abs(x.mean()) < 1e-14
+
+
+def test_stop_rule_and_iteration_history():
+    d = disc_for(O.Octree(problems.uniform_spec(5)))
+    rhs = problems.rhs_manufactured(1, d.tree.level, d.tree.ijk)
+    x, info = K.pcg(d.A, rhs, hierarchy(d).vcycle, 1e-10, 100)
+    h = info["hist"]
+    assert h[-1] <= 1e-10 < h[-2]
+    assert len(h) == info["iters"] + 1
+    assert info["true"] <= 2e-10
+    # per-iteration reduction is at least 10x on the uniform Poisson problem
+    rates = np.array(h[1:]) / np.array(h[:-1])
+    assert np.exp(np.log(rates).mean()) < 0.1
+
+
+def test_zero_rhs_and_max_iter():
+    d = disc_for(O.Octree(problems.uniform_spec(3)))
+    x, info = K.pcg(d.A, np.zeros(d.tree.n), hierarchy(d).vcycle, 1e-10, 10)
+    assert info["iters"] == 0 and np.all(x == 0)
+    rhs = problems.rhs_manufactured(1, d.tree.level, d.tree.ijk)
+    x, info = K.pcg(d.A, rhs, hierarchy(d).vcycle, 1e-10, 1)
+    assert info["iters"] == 1 and info["status"] == 1
