@@ -1,0 +1,244 @@
+/*
+ * mfmg.h -- C ABI of the MI355X matrix-free octree multigrid PCG solver.
+ *
+ * The solver computes p with A p = rhs, where A is the volume-integrated
+ * operator -div(beta grad .) on a 2:1-balanced adaptive octree with cut
+ * cells (paper: "Matrix-Free Multigrid with Algebraically Consistent
+ * Coarsening on Adaptive Octrees", Section 2.1 Eqs. (2)-(3), Section 3.1
+ * Eqs. (5)-(10)), by preconditioned conjugate gradients (Algorithm 1) with
+ * one FAS-style multigrid cycle (Algorithm 4, coarse operators from
+ * Algorithm 3) as the preconditioner.
+ *
+ * Conventions shared by every call
+ *   - Cells: a leaf is a cell (level l, i, j, k) of size h = 2^-l on the
+ *     unit cube.  Leaves are grouped in 4x4x4 bricks (the refinement unit).
+ *     Canonical leaf order is ascending Morton key of the cell's min corner
+ *     on the 2^max_level grid (x in the least significant interleaved bit);
+ *     equivalently bricks in Morton order, 64 cells per brick, cells in
+ *     local Morton order.  Every leaf vector (rhs, p, lambda, dL/dp) is a
+ *     contiguous array of n_leaves doubles in that order.
+ *   - Directions 0..5 are -x, +x, -y, +y, -z, +z.
+ *   - Faces: a face between leaves of different levels belongs to the finer
+ *     leaf, between equal levels to the leaf on its + side, a wall face to
+ *     its leaf.  Canonical face order is (owner leaf, direction).
+ *   - "device" pointers are HIP device memory of the current device; "host"
+ *     pointers are ordinary host memory.  The caller owns every buffer it
+ *     passes; the library owns only the objects it returns, which the
+ *     matching mfmg_destroy_* call frees.
+ *   - stream is a hipStream_t (NULL = the default stream).  Every call
+ *     enqueues its device work on that stream and returns after the work it
+ *     needs has completed; statistics are valid on return.
+ *   - Errors are reported by status code only; nothing throws across the
+ *     ABI.  mfmg_last_error() returns a thread-local message for the last
+ *     failing call of the calling thread.
+ */
+#ifndef MFMG_H
+#define MFMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MFMG_OK = 0,
+  MFMG_NOT_CONVERGED = 1,        /* warning: outputs hold the last iterate   */
+  MFMG_ERR_INVALID_ARG = -1,     /* NULL pointer, size or range violation    */
+  MFMG_ERR_TOPOLOGY = -2,        /* levels out of range, unbalanced input    */
+  MFMG_ERR_HIP = -3,             /* a HIP runtime call failed                */
+  MFMG_ERR_OOM = -4,             /* device or host allocation failed         */
+  MFMG_ERR_BREAKDOWN = -5,       /* (p,Ap) <= 0, (r,z) <= 0 or non-finite    */
+  MFMG_ERR_INCOMPATIBLE_RHS = -6 /* reserved: all-Neumann with 1^T rhs != 0  */
+} mfmg_status;
+
+typedef struct mfmg_octree mfmg_octree;
+typedef struct mfmg_coeffs mfmg_coeffs;
+typedef struct mfmg_hierarchy mfmg_hierarchy;
+
+/* Thread-local message of the last failing call ("" if none). */
+const char *mfmg_last_error(void);
+
+/* ------------------------------------------------------------------ octree
+ * Refinement predicates of the paper's grid generator (Section 4.1: a tile
+ * meeting the surface takes the finest level), applied to 4^3-cell nodes:
+ *   MFMG_SPHERE: the closed node box meets the shell
+ *                radius - band <= |x - center| <= radius + band;
+ *   MFMG_BOX:    the closed node box meets the boundary of the closed box
+ *                [lo, hi].
+ */
+enum { MFMG_SPHERE = 0, MFMG_BOX = 1 };
+
+typedef struct {
+  int kind;         /* MFMG_SPHERE or MFMG_BOX                               */
+  double center[3]; /* sphere centre                                         */
+  double radius;    /* sphere radius                                         */
+  double band;      /* half-width of the refinement shell (>= 0)             */
+  double lo[3];     /* box corners                                           */
+  double hi[3];
+} mfmg_prim;
+
+typedef struct {
+  int min_level;  /* cell level of the initial uniform grid, >= 2            */
+  int max_level;  /* finest cell level, min_level <= max_level <= 12         */
+  int node_size;  /* cells per node edge; must be 4                          */
+  int n_prims;    /* number of refinement primitives (>= 0)                  */
+  const mfmg_prim *prims; /* host array of n_prims                           */
+} mfmg_refine_spec;
+
+/* Build the octree on the host (Section 3; 2:1 face balance).  For
+ * l = min_level .. max_level-1 every leaf node of level l whose closed box
+ * meets some primitive is split into 8; then coarse leaves are split to the
+ * least fixed point where face-neighbouring leaves differ by at most one
+ * level.  Host memory only; no device call.  *out receives a new object.
+ * Errors: INVALID_ARG (NULL, node_size != 4, bad levels or primitive kind). */
+mfmg_status mfmg_build_octree(const mfmg_refine_spec *spec, mfmg_octree **out);
+
+/* Sizes of the octree: leaf cells, faces, leaf bricks (any output may be
+ * NULL).  Host only. */
+mfmg_status mfmg_octree_info(const mfmg_octree *tree, int64_t *n_leaves,
+                             int64_t *n_faces, int64_t *n_leaf_bricks);
+
+/* Leaves in canonical order: level[n] and ijk[3n] (i, j, k at that level).
+ * Host buffers of n_leaves and 3 n_leaves entries. */
+mfmg_status mfmg_octree_leaves(const mfmg_octree *tree, uint8_t *level,
+                               int32_t *ijk);
+
+/* Faces in canonical order (host buffers of n_faces entries each):
+ *   owner: owning leaf; dir: direction 0..5 from the owner;
+ *   other: leaf across the face (same-level neighbour or coarser leaf) or
+ *          -1 for a wall face;
+ *   kind:  0 wall, 1 same level, 2 T-junction (owner finer than other). */
+mfmg_status mfmg_octree_faces(const mfmg_octree *tree, int64_t *owner,
+                              int8_t *dir, int64_t *other, int8_t *kind);
+
+void mfmg_destroy_octree(mfmg_octree *tree);
+
+/* ------------------------------------------------------------ coefficients
+ * Four coefficients per cell (Eq. 3) as magnitudes: the diagonal c and the
+ * -x, -y, -z face coefficients, with face coefficient
+ *   same level or T-junction (fine side): beta S / h,
+ *   Dirichlet wall: beta S / (theta h), Neumann wall: 0,
+ * S = h^2 the owner's face area and h its size; the coarse side of a
+ * T-junction face carries the sum of its fine sub-face coefficients over 2
+ * (Section 3.1).  A cell is a degree of freedom iff c != 0.
+ */
+enum { MFMG_NEUMANN = 0, MFMG_DIRICHLET = 1 };
+
+typedef struct {
+  int bc[6];      /* per domain wall (-x,+x,-y,+y,-z,+z): MFMG_NEUMANN or    */
+                  /* MFMG_DIRICHLET (p = 0 outside)                           */
+  double theta;   /* Dirichlet wall distance in cell sizes, (0, 1]; 0.5 puts */
+                  /* p = 0 on the face, 1 is the paper's Dirichlet-cell rule  */
+} mfmg_bc;
+
+/* Assemble leaf coefficients on the device from per-face beta (device,
+ * n_faces doubles in canonical face order, each >= 0).  Uploads the brick
+ * topology on first use.  *out receives a new object that references tree
+ * (tree must outlive it).  Errors: INVALID_ARG, HIP, OOM. */
+mfmg_status mfmg_assemble_coeffs(const mfmg_octree *tree,
+                                 const double *face_beta, const mfmg_bc *bc,
+                                 void *stream, mfmg_coeffs **out);
+
+/* Copy leaf coefficients to a device buffer of 4 n_leaves doubles laid out
+ * as [c | kx | ky | kz], each in canonical leaf order. */
+mfmg_status mfmg_coeffs_leaf(const mfmg_coeffs *coeffs, double *out,
+                             void *stream);
+
+void mfmg_destroy_coeffs(mfmg_coeffs *coeffs);
+
+/* --------------------------------------------------------------- hierarchy
+ * Multigrid levels max_level .. coarsest_level.  Inner-cell coefficients
+ * come from Algorithm 3 (Section 2.5) with restriction scale alpha.
+ * precision MFMG_FP64: the cycle runs in FP64.  MFMG_MIXED: the cycle runs
+ * in FP32 with FP32 leaf coefficients and FP16 inner coefficients stored as
+ * c / h_l; the outer PCG, its dot products and the true residual stay FP64.
+ */
+enum { MFMG_FP64 = 0, MFMG_MIXED = 1 };
+
+typedef struct {
+  int nu_pre;         /* RBGS iterations before the coarse correction (2)    */
+  int nu_post;        /* RBGS iterations after it (2)                         */
+  int nu_coarse;      /* RBGS iterations on the coarsest level (10)           */
+  int mu;             /* cycle index: 1 = V-cycle, 2 = W-cycle               */
+  int coarsest_level; /* 2 <= coarsest_level <= min_level (3)                */
+  double alpha;       /* restriction scale, R = P^T / alpha (2)              */
+  double beta_mg;     /* coarse-correction factor applied at restriction (2) */
+  int precision;      /* MFMG_FP64 or MFMG_MIXED                             */
+} mfmg_mg_params;
+
+/* Build the hierarchy for coeffs (which must outlive it). */
+mfmg_status mfmg_build_hierarchy(const mfmg_coeffs *coeffs,
+                                 const mfmg_mg_params *params, void *stream,
+                                 mfmg_hierarchy **out);
+
+/* Inner-cell coefficients of one level, FP64, to a device buffer of
+ * 4 * 64 * n_bricks(level) doubles ([c|kx|ky|kz] per brick of 64 cells, in
+ * the order returned by mfmg_hierarchy_level_bricks); leaf bricks of that
+ * level hold their assembled coefficients. */
+mfmg_status mfmg_hierarchy_level_coeffs(const mfmg_hierarchy *h, int level,
+                                        double *out, void *stream);
+
+/* Bricks of one level: count, and (if coords != NULL) host int32 triples of
+ * brick coordinates (brick size 4 cells) and is_leaf flags (may be NULL). */
+mfmg_status mfmg_hierarchy_level_bricks(const mfmg_hierarchy *h, int level,
+                                        int64_t *count, int32_t *coords,
+                                        uint8_t *is_leaf);
+
+void mfmg_destroy_hierarchy(mfmg_hierarchy *h);
+
+/* ------------------------------------------------------------------- solve */
+typedef struct {
+  double rtol;    /* stop when ||r_k||_2 <= rtol ||r_0||_2 (1e-10)           */
+  int max_iter;   /* iteration cap (200)                                      */
+  int null_space; /* -1 auto (on iff no Dirichlet wall), 0 off, 1 on: shift */
+                  /* the residual to zero mean over active cells (Sec. 2.2)  */
+} mfmg_solve_params;
+
+typedef struct {
+  int iters;              /* PCG iterations performed                        */
+  int status;             /* mfmg_status of the solve                        */
+  double rel_resid_recur; /* ||r_k|| / ||r_0|| of the recurrence             */
+  double rel_resid_true;  /* ||rhs - A p|| / ||r_0|| recomputed in FP64      */
+  double seconds;         /* device time of the solve (HIP events)           */
+} mfmg_solve_stats;
+
+/* Solve A p = rhs (Algorithm 1, x0 = 0).  rhs, p: device, n_leaves doubles
+ * in canonical order; entries of inactive leaves are ignored on input and
+ * set to 0 on output.  hist (host, may be NULL) receives max_iter + 1
+ * relative residuals (the first iters + 1 are meaningful).
+ * Returns OK, NOT_CONVERGED (p holds the last iterate), BREAKDOWN, or an
+ * error. */
+mfmg_status mfmg_pcg_solve(mfmg_hierarchy *h, const double *rhs, double *p,
+                           const mfmg_solve_params *params, void *stream,
+                           mfmg_solve_stats *stats, double *hist);
+
+/* Adjoint of the solve: lambda with A^T lambda = dL_dp, preconditioned by
+ * the exact transpose of the cycle, then per face
+ *   dL/dbeta_f = -lambda^T (dA/dbeta_f) p
+ * (0 at Neumann walls and where a side of the face is inactive).
+ * p, dL_dp, lambda: device, n_leaves; dL_dbeta: device, n_faces. */
+mfmg_status mfmg_pcg_solve_adjoint(mfmg_hierarchy *h, const double *p,
+                                   const double *dL_dp, double *lambda,
+                                   double *dL_dbeta,
+                                   const mfmg_solve_params *params,
+                                   void *stream, mfmg_solve_stats *stats);
+
+/* ------------------------------------------------ component entry points
+ * For parity tests of single steps.  Device vectors of n_leaves doubles. */
+
+/* y = A x (transpose = 0) or y = A^T x (transpose = 1), composite leaf
+ * operator with T-junction ghosts (Section 3.1). */
+mfmg_status mfmg_apply_operator(mfmg_hierarchy *h, const double *x, double *y,
+                                int transpose, void *stream);
+
+/* z = M r (transpose = 0: one cycle of Algorithm 4 from zero) or
+ * z = M^T r (transpose = 1); in the hierarchy's precision. */
+mfmg_status mfmg_apply_precond(mfmg_hierarchy *h, const double *r, double *z,
+                               int transpose, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MFMG_H */

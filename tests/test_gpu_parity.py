@@ -1,0 +1,115 @@
+"""GPU parity: the HIP path through the C ABI against the oracle on the same
+seeded inputs (small members of every workload family, element by element)."""
+
+import numpy as np
+import pytest
+
+from gpu_fixtures import rel, small_cases
+
+pytestmark = pytest.mark.gpu
+
+CASES = small_cases()
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    print(f"\n[case {request.param}]", flush=True)
+    return CASES[request.param]()
+
+
+def test_topology_bit_exact(case):
+    lev, ijk = case.tree.leaves()
+    assert np.array_equal(lev, case.T.level)
+    assert np.array_equal(ijk, case.T.ijk)
+    owner, d, other, kind = case.tree.faces()
+    assert np.array_equal(owner, case.disc.face_owner)
+    assert np.array_equal(d, case.disc.face_dir)
+    assert np.array_equal(other, case.disc.face_other)
+    assert np.array_equal(kind, case.disc.face_kind)
+
+
+def test_leaf_coefficients(case):
+    from paper_2604_18886_amd import mfmg
+    co = mfmg.assemble_coeffs(case.tree, case.device(case.beta), case.bc, case.theta)
+    got = co.leaf_coeffs().cpu().numpy()
+    want = np.stack([case.disc.c, case.disc.dirk[:, 0], case.disc.dirk[:, 2],
+                     case.disc.dirk[:, 4]])
+    scale = np.abs(want).max()
+    assert np.abs(got - want).max() <= 1e-15 * scale
+
+
+def test_level_coefficients_algorithm3(case):
+    h = case.gpu_hierarchy()
+    H = case.hier
+    for l in range(H.L, H.lc - 1, -1):
+        coords, leaf = h.level_bricks(l)
+        got = h.level_coeffs(l).cpu().numpy()  # (nb, 4, 64)
+        Lv = H.levels[l]
+        # map oracle level cells into (brick, local morton)
+        ijk = Lv.ijk
+        bc = ijk // 4
+        loc = ijk % 4
+        m = ((loc[:, 0] & 1) | ((loc[:, 1] & 1) << 1) | ((loc[:, 2] & 1) << 2)
+             | ((loc[:, 0] & 2) << 2) | ((loc[:, 1] & 2) << 3) | ((loc[:, 2] & 2) << 4))
+        key = {tuple(c): i for i, c in enumerate(coords)}
+        bidx = np.array([key[tuple(c)] for c in bc])
+        want = np.stack([Lv.c, Lv.kx, Lv.ky, Lv.kz], axis=1)
+        g = got[bidx, :, m]
+        scale = np.abs(want).max()
+        assert np.abs(g - want).max() <= 1e-14 * scale, l
+
+
+def test_operator_and_transpose(case):
+    from paper_2604_18886_amd import mfmg
+    h = case.gpu_hierarchy()
+    rng = np.random.default_rng(7)
+    x = np.where(case.disc.active, rng.uniform(-1, 1, case.T.n), 0.0)
+    y = mfmg.apply_operator(h, case.device(x)).cpu().numpy()
+    want = case.disc.A @ x
+    assert np.abs(y - want).max() <= 1e-13 * np.abs(want).max()
+    yt = mfmg.apply_operator(h, case.device(x), transpose=True).cpu().numpy()
+    wt = case.disc.A.T @ x
+    assert np.abs(yt - wt).max() <= 1e-13 * np.abs(wt).max()
+
+
+def test_one_cycle_fp64(case):
+    from paper_2604_18886_amd import mfmg
+    h = case.gpu_hierarchy()
+    rng = np.random.default_rng(8)
+    r = np.where(case.disc.active, rng.uniform(-1, 1, case.T.n), 0.0)
+    z = mfmg.apply_precond(h, case.device(r)).cpu().numpy()
+    want = case.hier.vcycle(r)
+    assert rel(z, want) <= 1e-12
+
+
+def test_one_cycle_mixed_close(case):
+    from paper_2604_18886_amd import mfmg
+    h = case.gpu_hierarchy(precision=mfmg.MIXED)
+    rng = np.random.default_rng(9)
+    r = np.where(case.disc.active, rng.uniform(-1, 1, case.T.n), 0.0)
+    z = mfmg.apply_precond(h, case.device(r)).cpu().numpy()
+    want = case.hier.vcycle(r)
+    # FP32 arithmetic with FP16 coarse coefficients: a perturbed preconditioner
+    assert rel(z, want) <= 2e-2
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solve_matches_oracle(case, precision):
+    from paper_2604_18886_amd import mfmg
+    h = case.gpu_hierarchy(precision=precision)
+    p, st, hist = mfmg.pcg_solve(h, case.device(case.rhs), rtol=1e-10, history=True)
+    p = p.cpu().numpy()
+    x, info = case.oracle_solve(1e-13)
+    print(f"  precision={precision} gpu iters={st['iters']} oracle(1e-13) iters={info['iters']}"
+          f" true={st['rel_resid_true']:.2e} err={rel(p, x):.2e}", flush=True)
+    assert st["status"] == 0
+    assert st["rel_resid_true"] <= 1.5e-10
+    assert rel(p, x) <= 1e-9
+    # iteration count of the FP64 path equals the oracle's at the same rtol
+    if precision == 0:
+        _, info10 = case.oracle_solve(1e-10)
+        assert abs(st["iters"] - info10["iters"]) <= 1
+        assert np.allclose(hist[: len(info10["hist"])], info10["hist"][: len(hist)],
+                           rtol=1e-6, atol=1e-14)
+    # inactive leaves are zero on output
+    assert np.all(p[~case.disc.active] == 0.0)
