@@ -237,6 +237,22 @@ mfmg_status mfmg_apply_operator(mfmg_hierarchy *h, const double *x, double *y,
 mfmg_status mfmg_apply_precond(mfmg_hierarchy *h, const double *r, double *z,
                                int transpose, void *stream);
 
+/* ------------------------------------------------------------ measurement
+ * Average device time of one launch of a hot-path step, measured with HIP
+ * events on `stream` over `reps` back-to-back launches, and the algorithmic
+ * HBM bytes of one launch (each array the step must read or write counted
+ * once; a half-sweep reads u and the three face coefficients of every cell
+ * and the right-hand side and diagonal of the updated half, and writes the
+ * updated half).
+ *   what = MFMG_PROFILE_SMOOTH: one colour half-sweep of level `level`;
+ *   what = MFMG_PROFILE_CYCLE:  one whole cycle (level ignored), its
+ *          right-hand side being the current residual buffer.
+ * The work vectors of h are overwritten. */
+enum { MFMG_PROFILE_SMOOTH = 0, MFMG_PROFILE_CYCLE = 1 };
+mfmg_status mfmg_profile(mfmg_hierarchy *h, int what, int level, int reps,
+                         void *stream, double *ms_per_launch,
+                         double *bytes_per_launch);
+
 #ifdef __cplusplus
 }
 #endif

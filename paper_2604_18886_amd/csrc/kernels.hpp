@@ -10,6 +10,8 @@
 // brick (256 values).
 #pragma once
 
+#include <type_traits>
+
 #include "device.hpp"
 
 namespace mfmg {
@@ -23,7 +25,15 @@ struct Topo {
   const int32_t *child;    // 8 per brick
   const int32_t *tplus;    // per leaf brick
   const uint64_t *act;     // per brick: active-cell mask
+  const uint32_t *flags;   // per brick: face kinds, see kFlag*
 };
+
+// Per-brick face flags: bit d (d = 0..5) the face is a T-junction (coarser
+// leaf beyond), bit 8 + d the same-level neighbour is an inner brick, bit
+// 16 + d the face is a domain wall.
+constexpr uint32_t kFlagT = 0x3fu;
+constexpr uint32_t kFlagInner = 0x3fu << 8;
+constexpr uint32_t kFlagWall = 0x3fu << 16;
 
 // Coefficient access for one multigrid level: leaf bricks read CL values,
 // inner bricks read CI values multiplied by iscale (FP16 inner coefficients
@@ -35,12 +45,18 @@ struct Coefs {
   const CL *tc;     // plus-side T-face coefficients, 48 per slot
   int64_t nlb;
   V iscale;
-  __device__ __forceinline__ V get(int64_t b, int comp, int m) const {
-    if (b < nlb) return V(leaf[b * 256 + comp * 64 + m]);
-    return V(inner[(b - nlb) * 256 + comp * 64 + m]) * iscale;
+  // When CL == CI the inner coefficients directly follow the leaf ones
+  // (one array over all bricks) and no branch is needed.
+  __device__ __forceinline__ V get(uint32_t b, int comp, int m) const {
+    if constexpr (std::is_same<CL, CI>::value) {
+      return V(leaf[b * 256u + comp * 64 + m]);
+    } else {
+      if (b < nlb) return V(leaf[b * 256u + comp * 64 + m]);
+      return V(inner[(b - uint32_t(nlb)) * 256u + comp * 64 + m]) * iscale;
+    }
   }
   __device__ __forceinline__ V tplus(int32_t slot, int a, int fidx) const {
-    return V(tc[int64_t(slot) * 48 + a * 16 + fidx]);
+    return V(tc[uint32_t(slot) * 48u + a * 16 + fidx]);
   }
 };
 
@@ -49,7 +65,7 @@ __device__ __forceinline__ T to_v(double x) { return T(x); }
 
 // Coarse cell (local Morton index inside the coarse leaf brick J) seen from
 // cell m of brick b across direction d at a T-junction.
-__device__ __forceinline__ int coarse_local(const Topo &T, int64_t b, int m, int d,
+__device__ __forceinline__ int coarse_local(const Topo &T, uint32_t b, int m, int d,
                                             int32_t J) {
   int a = d >> 1;
   int s = (d & 1) ? 1 : -1;
@@ -67,63 +83,125 @@ __device__ __forceinline__ int coarse_local(const Topo &T, int64_t b, int m, int
 // own cell of brick b):  (A u)_m = c u_m - sum_d k_d v_d  with v_d the
 // same-level neighbour value, 0 at a wall, or at a T-junction the ghost
 // u_m + (u_J - mean_active_siblings(u)) / 2, u_J read from the coarser level.
+// All neighbour loads are issued before any arithmetic; the T-junction work
+// sits behind a wave-uniform branch on the brick's face flags.
 // ---------------------------------------------------------------------------
 template <class V, class CL, class CI>
 __device__ __forceinline__ V level_Au(const Topo &T, const Coefs<V, CL, CI> &cf,
-                                      const V *__restrict__ U, int64_t b, int m, V u,
-                                      V c, V k0, V k1, V k2, uint64_t amask) {
-  // mean of the active siblings (aligned group of 8 lanes)
-  bool act = (amask >> m) & 1ull;
-  V s = group8_sum(act ? u : V(0));
-  int cnt = __popcll((amask >> (m & 56)) & 0xffull);
-  V ubar = cnt ? s / V(cnt) : V(0);
-  V acc = c * u;
+                                      const V *__restrict__ U, uint32_t b, int m, V u,
+                                      V c, V k0, V k1, V k2, uint64_t amask, uint32_t flags,
+                                      const int32_t (&nb6)[6]) {
+  V v[6], k[6];
 #pragma unroll
   for (int d = 0; d < 6; ++d) {
     int a = d >> 1;
     int p = dev_partner(m, d);
     V kown = a == 0 ? k0 : (a == 1 ? k1 : k2);
-    V v = shfl(u, p);
-    V kp = shfl(kown, p);
-    V k = (d & 1) ? kp : kown;
-    if (dev_outside(m, d)) {
-      int32_t nb = T.nbr[6 * b + d];
-      if (nb >= 0) {
-        v = U[int64_t(nb) * 64 + p];
-        if (d & 1) k = cf.get(nb, 1 + a, p);
-      } else if (nb == dWall) {
-        v = V(0);
-      } else {
-        int32_t J = dev_decode_coarse(nb);
-        V uJ = U[int64_t(J) * 64 + coarse_local(T, b, m, d, J)];
-        v = u + (uJ - ubar) * V(0.5);
-        if (d & 1) k = cf.tplus(T.tplus[b], a, dev_face_index(m, a));
+    v[d] = shfl(u, p);
+    k[d] = (d & 1) ? shfl(kown, p) : kown;
+  }
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    int p = dev_partner(m, d);
+    if (dev_outside(m, d) && nb6[d] >= 0) {
+      v[d] = U[uint32_t(nb6[d]) * 64u + p];
+      if (d & 1) k[d] = cf.get(nb6[d], 1 + (d >> 1), p);
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < 6; ++d)
+    if (dev_outside(m, d) && ((flags >> (16 + d)) & 1u)) v[d] = V(0);
+  if (flags & kFlagT) {
+    bool act = (amask >> m) & 1ull;
+    V s = group8_sum(act ? u : V(0));
+    int cnt = __popcll((amask >> (m & 56)) & 0xffull);
+    V ubar = cnt ? s / V(cnt) : V(0);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      if (((flags >> d) & 1u) && dev_outside(m, d)) {
+        int32_t J = dev_decode_coarse(nb6[d]);
+        V uJ = U[uint32_t(J) * 64u + coarse_local(T, b, m, d, J)];
+        v[d] = u + (uJ - ubar) * V(0.5);
+        if (d & 1) k[d] = cf.tplus(T.tplus[b], d >> 1, dev_face_index(m, d >> 1));
       }
     }
-    acc -= k * v;
   }
+  V acc = c * u;
+#pragma unroll
+  for (int d = 0; d < 6; ++d) acc -= k[d] * v[d];
   return acc;
 }
 
-// Composite leaf operator (the PCG operator, FP64).  Differs from the level
-// operator where a leaf's same-level neighbour is an inner cell P: there the
-// value is the mean of P's active children (leaves one level finer) and, for
-// a + face, the coefficient is the sum of those children's face
-// coefficients over 2.  TRANS = true gives the transposed operator, whose
-// T-junction blocks are the transposes of the rank-one blocks of A.
-template <bool TRANS>
+// Composite leaf operator (the PCG operator, FP64), forward.  X and C cover
+// all bricks: where a leaf's same-level neighbour is an inner cell P, X holds
+// the mean of P's active children (written by k_average_up) and C holds P's
+// Algorithm 3 coefficients, whose face coefficient is the sum of the fine
+// sub-face coefficients over 2, i.e. the coarse side of the T-junction
+// (Section 3.1).  The fine side uses the ghost of Eq. (10).
 __device__ __forceinline__ double composite_Au(const Topo &T, const double *__restrict__ C,
                                                const double *__restrict__ TC,
-                                               const double *__restrict__ X, int64_t b,
+                                               const double *__restrict__ X, uint32_t b,
                                                int m, double u, double c, double k0,
-                                               double k1, double k2, uint64_t amask) {
-  bool act = (amask >> m) & 1ull;
-  double s = group8_sum(act ? u : 0.0);
-  int cnt = __popcll((amask >> (m & 56)) & 0xffull);
-  double ubar = cnt ? s / double(cnt) : 0.0;
-  double acc = c * u;
-  double tpart = 0.0;  // TRANS: this cell's sum of (k/2)(u_m - u_J) over its T-faces
+                                               double k1, double k2, uint64_t amask,
+                                               uint32_t flags, const int32_t (&nb6)[6]) {
+  double v[6], k[6];
 #pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    int a = d >> 1;
+    int p = dev_partner(m, d);
+    double kown = a == 0 ? k0 : (a == 1 ? k1 : k2);
+    v[d] = shfl(u, p);
+    k[d] = (d & 1) ? shfl(kown, p) : kown;
+  }
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    int p = dev_partner(m, d);
+    if (dev_outside(m, d) && nb6[d] >= 0) {
+      v[d] = X[uint32_t(nb6[d]) * 64u + p];
+      if (d & 1) k[d] = C[uint32_t(nb6[d]) * 256u + (1 + (d >> 1)) * 64 + p];
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < 6; ++d)
+    if (dev_outside(m, d) && ((flags >> (16 + d)) & 1u)) v[d] = 0.0;
+  bool act = (amask >> m) & 1ull;
+  if (flags & kFlagT) {
+    double s = group8_sum(act ? u : 0.0);
+    int cnt = __popcll((amask >> (m & 56)) & 0xffull);
+    double ubar = cnt ? s / double(cnt) : 0.0;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      if (((flags >> d) & 1u) && dev_outside(m, d)) {
+        int32_t J = dev_decode_coarse(nb6[d]);
+        double uJ = X[uint32_t(J) * 64u + coarse_local(T, b, m, d, J)];
+        v[d] = u + (uJ - ubar) * 0.5;
+        if (d & 1)
+          k[d] = TC[uint32_t(T.tplus[b]) * 48u + (d >> 1) * 16 + dev_face_index(m, d >> 1)];
+      }
+    }
+  }
+  double acc = c * u;
+#pragma unroll
+  for (int d = 0; d < 6; ++d) acc -= k[d] * v[d];
+  return act ? acc : 0.0;
+}
+
+// Transposed composite operator (adjoint path).  Its T-junction blocks are
+// the transposes of the rank-one blocks of A: a fine cell's row gets, for
+// every sibling, (1/n) sum over the sibling group's T-faces of
+// (k/2)(x_i - x_J); a coarse leaf's row gets - sum_f (k_f/2) x_f over the
+// fine face cells f instead of K_F times their parent's mean.  X is a leaf
+// vector; inner neighbours are read through their children.
+__device__ __forceinline__ double composite_AuT(const Topo &T, const double *__restrict__ C,
+                                                const double *__restrict__ TC,
+                                                const double *__restrict__ X, uint32_t b,
+                                                int m, double u, double c, double k0,
+                                                double k1, double k2, uint64_t amask,
+                                                uint32_t flags, const int32_t (&nb6)[6]) {
+  bool act = (amask >> m) & 1ull;
+  int cnt = __popcll((amask >> (m & 56)) & 0xffull);
+  double acc = c * u;
+  double tpart = 0.0;  // this cell's sum of (k/2)(u_m - u_J) over its T-faces
   for (int d = 0; d < 6; ++d) {
     int a = d >> 1;
     int p = dev_partner(m, d);
@@ -132,66 +210,58 @@ __device__ __forceinline__ double composite_Au(const Topo &T, const double *__re
     double kp = shfl(kown, p);
     double k = (d & 1) ? kp : kown;
     if (dev_outside(m, d)) {
-      int32_t nb = T.nbr[6 * b + d];
+      int32_t nb = nb6[d];
       if (nb >= 0 && nb < T.nlb) {
-        v = X[int64_t(nb) * 64 + p];
-        if (d & 1) k = C[int64_t(nb) * 256 + (1 + a) * 64 + p];
+        v = X[uint32_t(nb) * 64u + p];
+        if (d & 1) k = C[uint32_t(nb) * 256u + (1 + a) * 64 + p];
       } else if (nb >= 0) {
-        // inner neighbour P = cell p of brick nb; its children are cells
-        // ((p & 7) << 3) | t of the leaf brick child[nb][p >> 3]
+        // inner neighbour P: - sum over P's children on the face toward this
+        // cell of (k_f / 2) x_f
         int32_t cb = T.child[8 * int64_t(nb) + (p >> 3)];
-        uint64_t cm = T.act[cb];
         int base = (p & 7) << 3;
-        int facebit = (d & 1) ? 0 : 1;  // children on P's face toward this cell
-        double sumv = 0.0, sumk = 0.0, sumkv = 0.0;
-        int n = 0;
+        int facebit = (d & 1) ? 0 : 1;
+        double sumkv = 0.0;
         for (int t = 0; t < 8; ++t) {
+          if (((t >> a) & 1) != facebit) continue;
           int q = base | t;
-          double xv = X[int64_t(cb) * 64 + q];
-          bool on = (cm >> q) & 1ull;
-          if (on) {
-            sumv += xv;
-            ++n;
-          }
-          if (((t >> a) & 1) == facebit) {
-            double kc;
-            if (d & 1) {
-              kc = C[int64_t(cb) * 256 + (1 + a) * 64 + q];
-            } else {
-              kc = TC[int64_t(T.tplus[cb]) * 48 + a * 16 + dev_face_index(q, a)];
-            }
-            sumk += kc * 0.5;
-            sumkv += kc * 0.5 * xv;
-          }
+          double kc = (d & 1) ? C[uint32_t(cb) * 256u + (1 + a) * 64 + q]
+                              : TC[uint32_t(T.tplus[cb]) * 48u + a * 16 + dev_face_index(q, a)];
+          sumkv += kc * 0.5 * X[uint32_t(cb) * 64u + q];
         }
-        if (d & 1) k = sumk;
-        if (TRANS) {
-          // row of the coarse cell in A^T: - sum_f (k_f / 2) x_f
-          acc -= sumkv;
-          continue;
-        }
-        v = n ? sumv / double(n) : 0.0;
+        acc -= sumkv;
+        continue;
       } else if (nb == dWall) {
         v = 0.0;
       } else {
         int32_t J = dev_decode_coarse(nb);
-        double uJ = X[int64_t(J) * 64 + coarse_local(T, b, m, d, J)];
-        if (d & 1) k = TC[int64_t(T.tplus[b]) * 48 + a * 16 + dev_face_index(m, a)];
-        if (TRANS) {
-          acc -= k * u;
-          tpart += k * 0.5 * (u - uJ);
-          continue;
-        }
-        v = u + (uJ - ubar) * 0.5;
+        double uJ = X[uint32_t(J) * 64u + coarse_local(T, b, m, d, J)];
+        if (d & 1) k = TC[uint32_t(T.tplus[b]) * 48u + a * 16 + dev_face_index(m, a)];
+        acc -= k * u;
+        tpart += k * 0.5 * (u - uJ);
+        continue;
       }
     }
     acc -= k * v;
   }
-  if (TRANS) {
-    double S = group8_sum(tpart);
-    if (act && cnt) acc += S / double(cnt);
-  }
+  double S = group8_sum(tpart);
+  if (act && cnt) acc += S / double(cnt);
   return act ? acc : 0.0;
+}
+
+// Mean of the active cells of each aligned sibling group of a leaf brick
+// with a T-face, written to the parent cells' slots of a full-size vector
+// (the value the composite operator reads for an inner neighbour).
+__device__ __forceinline__ void average_up(const Topo &T, double *__restrict__ X, uint32_t b,
+                                           int m, double x, uint64_t amask) {
+  bool act = (amask >> m) & 1ull;
+  double s = group8_sum(act ? x : 0.0);
+  int cnt = __popcll((amask >> (m & 56)) & 0xffull);
+  if ((m & 7) == 0) {
+    uint32_t P = uint32_t(T.parent[b]);
+    int32_t bx = T.coord[3 * b], by = T.coord[3 * b + 1], bz = T.coord[3 * b + 2];
+    int oct = (bx & 1) | ((by & 1) << 1) | ((bz & 1) << 2);
+    X[P * 64u + ((oct << 3) | (m >> 3))] = cnt ? s / double(cnt) : 0.0;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -239,7 +309,7 @@ __global__ void __launch_bounds__(kBlock) k_assemble(AssembleArgs A) {
         k = A.bc[d] == 1 ? A.beta[face_id(A, cell, d)] * (h / A.theta) : 0.0;
       } else if (nb >= 0 && nb < A.T.nlb) {
         if (d & 1) {
-          k = A.beta[face_id(A, int64_t(nb) * 64 + p, d - 1)] * h;
+          k = A.beta[face_id(A, uint32_t(nb) * 64u + p, d - 1)] * h;
         } else {
           k = A.beta[face_id(A, cell, d)] * h;
         }
@@ -253,7 +323,7 @@ __global__ void __launch_bounds__(kBlock) k_assemble(AssembleArgs A) {
         double acc = 0.0;
         for (int n = 0; n < 4; ++n) {
           int t = (abit << a) | ((n & 1) << o0) | ((n >> 1) << o1);
-          acc = acc + A.beta[face_id(A, int64_t(cb) * 64 + (base | t), d ^ 1)] * hf / 2.0;
+          acc = acc + A.beta[face_id(A, uint32_t(cb) * 64u + (base | t), d ^ 1)] * hf / 2.0;
         }
         k = acc;
       } else {
@@ -291,7 +361,7 @@ __global__ void __launch_bounds__(kBlock) k_coarsen(const int32_t *list, int64_t
   if (i >= n) return;
   int64_t b = list[i];
   int32_t cb = T.child[8 * b + (q >> 3)];
-  const double *cc = coef + int64_t(cb) * 256;
+  const double *cc = coef + uint32_t(cb) * 256u;
   int base = (q & 7) << 3;
   double c = 0.0, kx = 0.0, ky = 0.0, kz = 0.0;
   int cnt = 0;
@@ -355,12 +425,17 @@ struct LevelArgs {
 };
 
 template <class V, class CL, class CI>
-__device__ __forceinline__ void load_cell(const LevelArgs<V, CL, CI> &A, int64_t b, int m, V &c,
+__device__ __forceinline__ void load_cell(const LevelArgs<V, CL, CI> &A, uint32_t b, int m, V &c,
                                           V &k0, V &k1, V &k2) {
   c = A.cf.get(b, 0, m);
   k0 = A.cf.get(b, 1, m);
   k1 = A.cf.get(b, 2, m);
   k2 = A.cf.get(b, 3, m);
+}
+
+__device__ __forceinline__ void load_nbr(const Topo &T, uint32_t b, int32_t (&nb6)[6]) {
+#pragma unroll
+  for (int d = 0; d < 6; ++d) nb6[d] = T.nbr[6 * b + d];
 }
 
 // One colour half-sweep: u_m += (b_m - (A u)_m) / c_m on cells of the colour.
@@ -370,16 +445,18 @@ __global__ void __launch_bounds__(kBlock) k_smooth(LevelArgs<V, CL, CI> A, int c
   int64_t i = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
   int m = threadIdx.x & (kWave - 1);
   if (i >= A.n) return;
-  int64_t b = A.list[i];
+  uint32_t b = uint32_t(A.list[i]);
   V c, k0, k1, k2;
   load_cell(A, b, m, c, k0, k1, k2);
-  V u = A.U[b * 64 + m];
-  V rhs = A.B[b * 64 + m];
+  V u = A.U[b * 64u + m];
+  V rhs = A.B[b * 64u + m];
   uint64_t amask = A.T.act[b];
-  V Au = level_Au(A.T, A.cf, A.U, b, m, u, c, k0, k1, k2, amask);
+  int32_t nb6[6];
+  load_nbr(A.T, b, nb6);
+  V Au = level_Au(A.T, A.cf, A.U, b, m, u, c, k0, k1, k2, amask, A.T.flags[b], nb6);
   bool act = (amask >> m) & 1ull;
   int col = (dev_cx(m) + dev_cy(m) + dev_cz(m)) & 1;
-  if (act && col == colour) A.U[b * 64 + m] = u + (rhs - Au) / c;
+  if (act && col == colour) A.U[b * 64u + m] = u + (rhs - Au) / c;
 }
 
 // Residual, restriction and FAS initial guess from level l to its parents:
@@ -391,28 +468,30 @@ __global__ void __launch_bounds__(kBlock) k_restrict(LevelArgs<V, CL, CI> A, V s
   int64_t i = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
   int m = threadIdx.x & (kWave - 1);
   if (i >= A.n) return;
-  int64_t b = A.list[i];
+  uint32_t b = uint32_t(A.list[i]);
   V c, k0, k1, k2;
   load_cell(A, b, m, c, k0, k1, k2);
-  V u = A.U[b * 64 + m];
-  V rhs = A.B[b * 64 + m];
+  V u = A.U[b * 64u + m];
+  V rhs = A.B[b * 64u + m];
   uint64_t amask = A.T.act[b];
-  V Au = level_Au(A.T, A.cf, A.U, b, m, u, c, k0, k1, k2, amask);
+  int32_t nb6[6];
+  load_nbr(A.T, b, nb6);
+  V Au = level_Au(A.T, A.cf, A.U, b, m, u, c, k0, k1, k2, amask, A.T.flags[b], nb6);
   bool act = (amask >> m) & 1ull;
   V r = act ? rhs - Au : V(0);
   V rs = group8_sum(r);
   V us = group8_sum(act ? u : V(0));
   int cnt = __popcll((amask >> (m & 56)) & 0xffull);
   if ((m & 7) == 0) {
-    int64_t P = A.T.parent[b];
+    uint32_t P = uint32_t(A.T.parent[b]);
     // octant of this brick inside its parent
     int32_t bx = A.T.coord[3 * b], by = A.T.coord[3 * b + 1], bz = A.T.coord[3 * b + 2];
     int oct = (bx & 1) | ((by & 1) << 1) | ((bz & 1) << 2);
     int q = (oct << 3) | (m >> 3);
     V ust = cnt ? us / V(cnt) : V(0);
-    A.B[P * 64 + q] = rs * scale;
-    A.U[P * 64 + q] = ust;
-    A.Ustar[(P - A.T.nlb) * 64 + q] = ust;
+    A.B[P * 64u + q] = rs * scale;
+    A.U[P * 64u + q] = ust;
+    A.Ustar[(P - uint32_t(A.T.nlb)) * 64u + q] = ust;
   }
 }
 
@@ -423,15 +502,17 @@ __global__ void __launch_bounds__(kBlock) k_fas_rhs(LevelArgs<V, CL, CI> A) {
   int64_t i = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
   int m = threadIdx.x & (kWave - 1);
   if (i >= A.n) return;
-  int64_t b = A.list[i];
+  uint32_t b = uint32_t(A.list[i]);
   V c, k0, k1, k2;
   load_cell(A, b, m, c, k0, k1, k2);
-  V u = A.U[b * 64 + m];
+  V u = A.U[b * 64u + m];
   uint64_t amask = A.T.act[b];
-  V Au = level_Au(A.T, A.cf, A.U, b, m, u, c, k0, k1, k2, amask);
+  int32_t nb6[6];
+  load_nbr(A.T, b, nb6);
+  V Au = level_Au(A.T, A.cf, A.U, b, m, u, c, k0, k1, k2, amask, A.T.flags[b], nb6);
   bool act = (amask >> m) & 1ull;
-  V rhs = A.B[b * 64 + m];
-  A.B[b * 64 + m] = act ? rhs + Au : V(0);
+  V rhs = A.B[b * 64u + m];
+  A.B[b * 64u + m] = act ? rhs + Au : V(0);
 }
 
 // Prolongation of the FAS correction: u += u_P - u*_P on active cells.
@@ -441,15 +522,15 @@ __global__ void __launch_bounds__(kBlock) k_prolong(LevelArgs<V, CL, CI> A) {
   int64_t i = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
   int m = threadIdx.x & (kWave - 1);
   if (i >= A.n) return;
-  int64_t b = A.list[i];
+  uint32_t b = uint32_t(A.list[i]);
   uint64_t amask = A.T.act[b];
   if (!((amask >> m) & 1ull)) return;
-  int64_t P = A.T.parent[b];
+  uint32_t P = uint32_t(A.T.parent[b]);
   int32_t bx = A.T.coord[3 * b], by = A.T.coord[3 * b + 1], bz = A.T.coord[3 * b + 2];
   int oct = (bx & 1) | ((by & 1) << 1) | ((bz & 1) << 2);
   int q = (oct << 3) | (m >> 3);
-  V corr = A.U[P * 64 + q] - A.Ustar[(P - A.T.nlb) * 64 + q];
-  A.U[b * 64 + m] += corr;
+  V corr = A.U[P * 64u + q] - A.Ustar[(P - uint32_t(A.T.nlb)) * 64u + q];
+  A.U[b * 64u + m] += corr;
 }
 
 // Coarsest level: nu_coarse RBGS iterations in one workgroup, (R,B) for the
@@ -465,16 +546,18 @@ __global__ void __launch_bounds__(1024) k_coarsest(LevelArgs<V, CL, CI> A, int n
     for (int h2 = 0; h2 < 2; ++h2) {
       int colour = it < half ? h2 : 1 - h2;
       for (int64_t i = w; i < A.n; i += nw) {
-        int64_t b = A.list[i];
+        uint32_t b = uint32_t(A.list[i]);
         V c, k0, k1, k2;
         load_cell(A, b, m, c, k0, k1, k2);
-        V u = A.U[b * 64 + m];
-        V rhs = A.B[b * 64 + m];
+        V u = A.U[b * 64u + m];
+        V rhs = A.B[b * 64u + m];
         uint64_t amask = A.T.act[b];
-        V Au = level_Au(A.T, A.cf, A.U, b, m, u, c, k0, k1, k2, amask);
+        int32_t nb6[6];
+        load_nbr(A.T, b, nb6);
+        V Au = level_Au(A.T, A.cf, A.U, b, m, u, c, k0, k1, k2, amask, A.T.flags[b], nb6);
         bool act = (amask >> m) & 1ull;
         int col = (dev_cx(m) + dev_cy(m) + dev_cz(m)) & 1;
-        if (act && col == colour) A.U[b * 64 + m] = u + (rhs - Au) / c;
+        if (act && col == colour) A.U[b * 64u + m] = u + (rhs - Au) / c;
       }
       __threadfence_block();
       __syncthreads();

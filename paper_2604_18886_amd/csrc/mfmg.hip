@@ -88,6 +88,7 @@ struct DeviceTopology {
   DevBuf<int64_t> fbase;
   DevBuf<uint8_t> fmask;
   DevBuf<uint64_t> act;
+  DevBuf<uint32_t> flags;              // per-brick face flags
   DevBuf<int32_t> lists;               // concatenated per-level lists
   std::vector<int64_t> all_off, all_n; // per level: offset/count of all bricks
   std::vector<int64_t> in_off, in_n;   // per level: inner bricks
@@ -115,7 +116,8 @@ struct mfmg_hierarchy {
   // work vectors
   DevBuf<double> U64, B64, S64;  // FP64 cycle: nb*64, nb*64, (nb-nlb)*64
   DevBuf<float> U32, B32, S32;   // mixed cycle
-  DevBuf<double> r, pd, Ap;      // PCG (r aliases B64 in FP64 mode)
+  DevBuf<double> r, pd, Ap;      // PCG (r aliases B64 in FP64 mode); pd is full-size
+  DevBuf<double> Xf;             // full-size scratch for operator applications
   DevBuf<double> partials;
   DevBuf<Scalars> S;
   DevBuf<double> hist;
@@ -226,6 +228,15 @@ static void upload_topology(const Topology &T, DeviceTopology &D, hipStream_t s)
   D.level.upload(T.level, s);
   D.fbase.upload(T.cell_fbase, s);
   D.fmask.upload(T.cell_fmask, s);
+  std::vector<uint32_t> flags(T.n_bricks, 0u);
+  for (int64_t b = 0; b < T.n_bricks; ++b)
+    for (int d = 0; d < 6; ++d) {
+      int32_t n = T.nbr[6 * b + d];
+      if (n <= kCoarseBase) flags[b] |= 1u << d;
+      else if (n == kWall) flags[b] |= 1u << (16 + d);
+      else if (n >= T.n_leaf_bricks) flags[b] |= 1u << (8 + d);
+    }
+  D.flags.upload(flags, s);
   std::vector<int32_t> lists;
   int L = T.max_level;
   D.all_off.assign(L + 1, 0);
@@ -258,6 +269,7 @@ static Topo make_topo(const Topology &T, const DeviceTopology &D, const uint64_t
   t.child = D.child.p;
   t.tplus = D.tplus.p;
   t.act = act;
+  t.flags = D.flags.p;
   return t;
 }
 
@@ -417,7 +429,8 @@ extern "C" mfmg_status mfmg_build_hierarchy(const mfmg_coeffs *co, const mfmg_mg
       h->B64.alloc(size_t(nb) * 64);
       h->S64.alloc(size_t(nb - nlb) * 64 + 1);
     }
-    h->pd.alloc(size_t(N));
+    h->pd.alloc(size_t(nb) * 64);
+    h->Xf.alloc(size_t(nb) * 64);
     h->Ap.alloc(size_t(N));
     h->partials.alloc(4096);
     h->S.alloc(1);
@@ -564,19 +577,19 @@ struct PcgArgs {
   double *hist;
 };
 
-__device__ __forceinline__ void leaf_cell(const PcgArgs &P, int64_t b, int m, double &c,
+__device__ __forceinline__ void leaf_cell(const PcgArgs &P, uint32_t b, int m, double &c,
                                           double &k0, double &k1, double &k2) {
-  const double *cf = P.C + b * 256;
+  const double *cf = P.C + b * 256u;
   c = cf[m];
   k0 = cf[64 + m];
   k1 = cf[128 + m];
   k2 = cf[192 + m];
 }
 
-#define BRICK_LOOP(P)                                                           \
-  int m = threadIdx.x & (kWave - 1);                                            \
-  for (int64_t b = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;  \
-       b < (P).T.nlb; b += int64_t(gridDim.x) * kWavesPerBlock)
+#define BRICK_LOOP(P)                                                               \
+  int m = threadIdx.x & (kWave - 1);                                                \
+  for (uint32_t b = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;              \
+       b < uint32_t((P).T.nlb); b += gridDim.x * kWavesPerBlock)
 
 // r = rhs on active cells, x = 0, ||r||^2
 template <class V>
@@ -585,10 +598,10 @@ __global__ void __launch_bounds__(kBlock) k_pcg_init(PcgArgs P, const double *rh
   double part = 0.0;
   BRICK_LOOP(P) {
     bool act = (P.T.act[b] >> m) & 1ull;
-    double v = act ? rhs[b * 64 + m] : 0.0;
-    r[b * 64 + m] = v;
-    if (r_low) r_low[b * 64 + m] = V(v);
-    x[b * 64 + m] = 0.0;
+    double v = act ? rhs[b * 64u + m] : 0.0;
+    r[b * 64u + m] = v;
+    if (r_low) r_low[b * 64u + m] = V(v);
+    x[b * 64u + m] = 0.0;
     part += v * v;
   }
   Scalars *S = P.S;
@@ -611,7 +624,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_rz(PcgArgs P, const double *r, c
                                                    int first) {
   if (P.S->done) return;
   double part = 0.0;
-  BRICK_LOOP(P) { part += r[b * 64 + m] * double(z[b * 64 + m]); }
+  BRICK_LOOP(P) { part += r[b * 64u + m] * double(z[b * 64u + m]); }
   Scalars *S = P.S;
   block_reduce_finish(part, P.partials, &S->ticket[1], [&](double tot) {
     if (!(tot > 0.0) || !(tot < INFINITY)) {
@@ -630,10 +643,13 @@ __global__ void __launch_bounds__(kBlock) k_pcg_p(PcgArgs P, const V *z, double 
   if (P.S->done) return;
   double beta = P.S->beta;
   BRICK_LOOP(P) {
-    bool act = (P.T.act[b] >> m) & 1ull;
-    double v = double(z[b * 64 + m]);
-    if (!first) v = v + beta * p[b * 64 + m];
-    p[b * 64 + m] = act ? v : 0.0;
+    uint64_t amask = P.T.act[b];
+    bool act = (amask >> m) & 1ull;
+    double v = double(z[b * 64u + m]);
+    if (!first) v = v + beta * p[b * 64u + m];
+    v = act ? v : 0.0;
+    p[b * 64u + m] = v;
+    if (P.T.flags[b] & kFlagT) average_up(P.T, p, b, m, v, amask);
   }
 }
 
@@ -644,9 +660,12 @@ __global__ void __launch_bounds__(kBlock) k_pcg_Ap(PcgArgs P, const double *p, d
   BRICK_LOOP(P) {
     double c, k0, k1, k2;
     leaf_cell(P, b, m, c, k0, k1, k2);
-    double u = p[b * 64 + m];
-    double y = composite_Au<false>(P.T, P.C, P.TC, p, b, m, u, c, k0, k1, k2, P.T.act[b]);
-    Ap[b * 64 + m] = y;
+    double u = p[b * 64u + m];
+    int32_t nb6[6];
+    load_nbr(P.T, b, nb6);
+    double y = composite_Au(P.T, P.C, P.TC, p, b, m, u, c, k0, k1, k2, P.T.act[b],
+                            P.T.flags[b], nb6);
+    Ap[b * 64u + m] = y;
     part += u * y;
   }
   Scalars *S = P.S;
@@ -670,7 +689,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_update(PcgArgs P, double *x, dou
   double alpha = P.S->alpha;
   double part = 0.0;
   BRICK_LOOP(P) {
-    int64_t i = b * 64 + m;
+    uint32_t i = b * 64u + m;
     x[i] = x[i] + alpha * p[i];
     double v = r[i] - alpha * Ap[i];
     r[i] = v;
@@ -691,14 +710,31 @@ __global__ void __launch_bounds__(kBlock) k_pcg_update(PcgArgs P, double *x, dou
   });
 }
 
-// y = A x or A^T x (component entry point), no reduction
+// copy a leaf vector into the leaf part of a full-size vector and write the
+// parent means that the composite operator reads for inner neighbours
+__global__ void __launch_bounds__(kBlock) k_full(PcgArgs P, const double *x, double *X) {
+  BRICK_LOOP(P) {
+    uint64_t amask = P.T.act[b];
+    double v = ((amask >> m) & 1ull) ? x[b * 64u + m] : 0.0;
+    X[b * 64u + m] = v;
+    if (P.T.flags[b] & kFlagT) average_up(P.T, X, b, m, v, amask);
+  }
+}
+
+// y = A X (X full-size, from k_full) or y = A^T x (x a leaf vector)
 template <bool TRANS>
 __global__ void __launch_bounds__(kBlock) k_apply(PcgArgs P, const double *x, double *y) {
   BRICK_LOOP(P) {
     double c, k0, k1, k2;
     leaf_cell(P, b, m, c, k0, k1, k2);
-    y[b * 64 + m] =
-        composite_Au<TRANS>(P.T, P.C, P.TC, x, b, m, x[b * 64 + m], c, k0, k1, k2, P.T.act[b]);
+    int32_t nb6[6];
+    load_nbr(P.T, b, nb6);
+    if (TRANS)
+      y[b * 64u + m] = composite_AuT(P.T, P.C, P.TC, x, b, m, x[b * 64u + m], c, k0, k1, k2,
+                                    P.T.act[b], P.T.flags[b], nb6);
+    else
+      y[b * 64u + m] = composite_Au(P.T, P.C, P.TC, x, b, m, x[b * 64u + m], c, k0, k1, k2,
+                                   P.T.act[b], P.T.flags[b], nb6);
   }
 }
 
@@ -709,10 +745,12 @@ __global__ void __launch_bounds__(kBlock) k_true_resid(PcgArgs P, const double *
   BRICK_LOOP(P) {
     double c, k0, k1, k2;
     leaf_cell(P, b, m, c, k0, k1, k2);
-    double y = composite_Au<false>(P.T, P.C, P.TC, x, b, m, x[b * 64 + m], c, k0, k1, k2,
-                                   P.T.act[b]);
+    int32_t nb6[6];
+    load_nbr(P.T, b, nb6);
+    double y = composite_Au(P.T, P.C, P.TC, x, b, m, x[b * 64u + m], c, k0, k1, k2,
+                            P.T.act[b], P.T.flags[b], nb6);
     bool act = (P.T.act[b] >> m) & 1ull;
-    double t = act ? rhs[b * 64 + m] - y : 0.0;
+    double t = act ? rhs[b * 64u + m] - y : 0.0;
     part += t * t;
   }
   Scalars *S = P.S;
@@ -752,12 +790,15 @@ extern "C" mfmg_status mfmg_apply_operator(mfmg_hierarchy *h, const double *x, d
   const Topology &T = h->co->tree->topo;
   try {
     PcgArgs P = pcg_args(h);
-    if (transpose)
+    if (transpose) {
       hipLaunchKernelGGL(k_apply<true>, dim3(grid_for(T.n_leaf_bricks)), dim3(kBlock), 0, s, P,
                          x, y);
-    else
+    } else {
+      hipLaunchKernelGGL(k_full, dim3(grid_for(T.n_leaf_bricks)), dim3(kBlock), 0, s, P, x,
+                         h->Xf.p);
       hipLaunchKernelGGL(k_apply<false>, dim3(grid_for(T.n_leaf_bricks)), dim3(kBlock), 0, s,
-                         P, x, y);
+                         P, (const double *)h->Xf.p, y);
+    }
     HIP_CHECK(hipGetLastError());
     HIP_CHECK(hipStreamSynchronize(s));
   } catch (const HipError &e) {
@@ -821,7 +862,9 @@ static void pcg_iterate(mfmg_hierarchy *h, const double *rhs, double *x, double 
     HIP_CHECK(hipStreamSynchronize(s));
     if (h->hostS->done) break;
   }
-  hipLaunchKernelGGL(k_true_resid, dim3(G), dim3(kBlock), 0, s, P, rhs, (const double *)x);
+  hipLaunchKernelGGL(k_full, dim3(grid_for(T.n_leaf_bricks)), dim3(kBlock), 0, s, P,
+                     (const double *)x, h->Xf.p);
+  hipLaunchKernelGGL(k_true_resid, dim3(G), dim3(kBlock), 0, s, P, rhs, (const double *)h->Xf.p);
   HIP_CHECK(hipGetLastError());
 }
 
@@ -882,4 +925,104 @@ extern "C" mfmg_status mfmg_pcg_solve_adjoint(mfmg_hierarchy *h, const double *p
   (void)h; (void)p; (void)dL_dp; (void)lambda; (void)dL_dbeta; (void)sp; (void)stream;
   (void)stats;
   return fail(MFMG_ERR_INVALID_ARG, "adjoint solve not available in this build");
+}
+
+// --------------------------------------------------------------------------
+// measurement
+// --------------------------------------------------------------------------
+namespace {
+
+// Algorithmic bytes of one half-sweep over the bricks of level l.
+double smooth_bytes(const mfmg_hierarchy *h, int l) {
+  const DeviceTopology &D = *h->co->dt;
+  bool mixed = h->prm.precision == MFMG_MIXED;
+  double V = mixed ? 4.0 : 8.0;
+  double CL = mixed ? 4.0 : 8.0, CI = mixed ? 2.0 : 8.0;
+  double n_in = double(D.in_n[l]) * 64, n_all = double(D.all_n[l]) * 64;
+  double n_leaf = n_all - n_in;
+  auto per = [&](double C) { return V + 0.5 * V + 0.5 * C + 3.0 * C + 0.5 * V; };
+  return n_leaf * per(CL) + n_in * per(CI);
+}
+
+// Algorithmic bytes of one whole cycle (all kernels of all levels).
+double cycle_bytes(const mfmg_hierarchy *h) {
+  const DeviceTopology &D = *h->co->dt;
+  const mfmg_mg_params &p = h->prm;
+  bool mixed = p.precision == MFMG_MIXED;
+  double V = mixed ? 4.0 : 8.0;
+  double CL = mixed ? 4.0 : 8.0, CI = mixed ? 2.0 : 8.0;
+  double total = double(h->co->tree->topo.n_leaves()) * V;  // zero the leaf iterate
+  // visits of each level per cycle: mu^(L - l)
+  for (int l = h->L; l >= h->lc; --l) {
+    double visits = std::pow(double(p.mu), double(h->L - l));
+    double n_in = double(D.in_n[l]) * 64, n_all = double(D.all_n[l]) * 64;
+    double n_leaf = n_all - n_in;
+    double cells_coef = n_leaf * 4.0 * CL + n_in * 4.0 * CI;  // 4 coefficients
+    if (l == h->lc) {
+      total += visits * 2.0 * p.nu_coarse * smooth_bytes(h, l);
+      continue;
+    }
+    double lvl = 2.0 * (p.nu_pre + p.nu_post) * smooth_bytes(h, l);
+    lvl += n_all * (2.0 * V + 3.0 * V / 8.0) + cells_coef;  // residual + restriction
+    double c_in = double(D.in_n[l - 1]) * 64;                 // FAS right-hand side
+    double c_coef = c_in * 4.0 * CI;
+    lvl += c_in * 3.0 * V + c_coef;
+    lvl += n_all * (2.0 * V + 2.0 * V / 8.0);                 // prolongation
+    total += visits * lvl;
+  }
+  return total;
+}
+
+}  // namespace
+
+extern "C" mfmg_status mfmg_profile(mfmg_hierarchy *h, int what, int level, int reps,
+                                    void *stream, double *ms_per_launch,
+                                    double *bytes_per_launch) {
+  if (!h || !ms_per_launch || reps < 1) return fail(MFMG_ERR_INVALID_ARG, "bad argument");
+  hipStream_t s = (hipStream_t)stream;
+  const Topology &T = h->co->tree->topo;
+  if (what == MFMG_PROFILE_SMOOTH && (level < h->lc || level > h->L))
+    return fail(MFMG_ERR_INVALID_ARG, "level out of range");
+  try {
+    hipEvent_t e0, e1;
+    HIP_CHECK(hipEventCreate(&e0));
+    HIP_CHECK(hipEventCreate(&e1));
+    bool mixed = h->prm.precision == MFMG_MIXED;
+    auto launch = [&]() {
+      if (what == MFMG_PROFILE_SMOOTH) {
+        if (mixed) {
+          Cycle<float, float, __half> c{h, h->coef32.p, h->coef16.p, h->tc32.p,
+                                        h->U32.p, h->B32.p, h->S32.p, nullptr, s};
+          auto A = c.args(level, false);
+          hipLaunchKernelGGL((k_smooth<float, float, __half>), dim3(grid_for(A.n)),
+                             dim3(kBlock), 0, s, A, 0);
+        } else {
+          Cycle<double, double, double> c{h, h->coef64.p,
+                                          h->coef64.p + T.n_leaf_bricks * 256,
+                                          h->co->tc.p, h->U64.p, h->B64.p, h->S64.p,
+                                          nullptr, s};
+          auto A = c.args(level, false);
+          hipLaunchKernelGGL((k_smooth<double, double, double>), dim3(grid_for(A.n)),
+                             dim3(kBlock), 0, s, A, 0);
+        }
+      } else {
+        run_cycle(h, s, nullptr);
+      }
+    };
+    launch();  // warm
+    HIP_CHECK(hipEventRecord(e0, s));
+    for (int i = 0; i < reps; ++i) launch();
+    HIP_CHECK(hipEventRecord(e1, s));
+    HIP_CHECK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms_per_launch = double(ms) / reps;
+    if (bytes_per_launch)
+      *bytes_per_launch = what == MFMG_PROFILE_SMOOTH ? smooth_bytes(h, level) : cycle_bytes(h);
+  } catch (const HipError &e) {
+    return fail(MFMG_ERR_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  }
+  return MFMG_OK;
 }

@@ -96,6 +96,9 @@ SIGNATURES = {
                                               ctypes.POINTER(SolveStats)]),
     "mfmg_apply_operator": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int, _VP]),
     "mfmg_apply_precond": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int, _VP]),
+    "mfmg_profile": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP,
+                                    ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double)]),
 }
 
 _lib = None
@@ -331,3 +334,16 @@ def apply_precond(h, r, transpose=False):
     z = torch.empty_like(r)
     _check(_lib.mfmg_apply_precond(h._h, _ptr(r), _ptr(z), int(transpose), _stream()))
     return z
+
+
+PROFILE_SMOOTH, PROFILE_CYCLE = 0, 1
+
+
+def profile(h, what, level=0, reps=20):
+    """(ms per launch, algorithmic bytes per launch) of a hot-path step,
+    measured with HIP events on the current stream."""
+    ms = ctypes.c_double()
+    by = ctypes.c_double()
+    _check(_lib.mfmg_profile(h._h, int(what), int(level), int(reps), _stream(),
+                             ctypes.byref(ms), ctypes.byref(by)))
+    return ms.value, by.value
