@@ -2,6 +2,7 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -11,12 +12,13 @@
 
 #include "../../include/mfmg.h"
 #include "kernels.hpp"
+#include "pcg_kernels.hpp"
 #include "topology.hpp"
 
 using namespace mfmg;
 
 // --------------------------------------------------------------------------
-// errors
+// errors and device buffers
 // --------------------------------------------------------------------------
 namespace {
 thread_local std::string g_err;
@@ -37,6 +39,11 @@ struct HipError {
     if (e_ != hipSuccess) throw HipError{e_, #x};      \
   } while (0)
 
+mfmg_status hip_fail(const HipError &e) {
+  return fail(e.e == hipErrorOutOfMemory ? MFMG_ERR_OOM : MFMG_ERR_HIP,
+              std::string(e.what) + ": " + hipGetErrorString(e.e));
+}
+
 template <class T>
 struct DevBuf {
   T *p = nullptr;
@@ -56,8 +63,8 @@ struct DevBuf {
   }
   void upload(const std::vector<T> &v, hipStream_t s) {
     alloc(v.size());
-    if (!v.empty()) HIP_CHECK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T),
-                                             hipMemcpyHostToDevice, s));
+    if (!v.empty())
+      HIP_CHECK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
   }
 };
 
@@ -65,13 +72,14 @@ inline unsigned grid_for(int64_t bricks) {
   int64_t g = (bricks + kWavesPerBlock - 1) / kWavesPerBlock;
   return unsigned(g > 0 ? g : 1);
 }
-inline unsigned grid_elems(int64_t n, int t) { return unsigned((n + t - 1) / t); }
+inline unsigned grid_elems(int64_t n, int t) { return unsigned(std::max<int64_t>(1, (n + t - 1) / t)); }
 
-// grid of the reduction kernels (grid-stride over leaf bricks)
+// grid of the Krylov kernels (grid-stride over leaf bricks, one partial sum
+// per workgroup)
+constexpr int64_t kMaxReduceBlocks = 2048;
 inline unsigned grid_reduce(int64_t bricks) {
   int64_t g = (bricks + kWavesPerBlock - 1) / kWavesPerBlock;
-  if (g > 2048) g = 2048;
-  return unsigned(g > 0 ? g : 1);
+  return unsigned(std::max<int64_t>(1, std::min(g, kMaxReduceBlocks)));
 }
 }  // namespace
 
@@ -82,23 +90,27 @@ struct mfmg_octree {
   Topology topo;
 };
 
+// Device view of the topology.  Device brick ids are level-major (leaf bricks
+// by descending level then Morton order; inner bricks likewise); perm maps a
+// host brick id (canonical leaf order, then inner bricks) to its device id.
 struct DeviceTopology {
-  DevBuf<int32_t> nbr, coord, parent, child, tplus;
-  DevBuf<int8_t> level;
-  DevBuf<int64_t> fbase;
-  DevBuf<uint8_t> fmask;
-  DevBuf<uint64_t> act;
-  DevBuf<uint32_t> flags;              // per-brick face flags
-  DevBuf<int32_t> lists;               // concatenated per-level lists
-  std::vector<int64_t> all_off, all_n; // per level: offset/count of all bricks
-  std::vector<int64_t> in_off, in_n;   // per level: inner bricks
-  DevBuf<int32_t> leaf_list;           // 0..nlb-1 (identity)
+  std::vector<int32_t> perm;          // host brick -> device brick
+  std::vector<BrickMeta> meta_host;   // device order, act = 0
+  DevBuf<BrickMeta> meta;
+  DevBuf<int32_t> child;              // 8 per device brick
+  DevBuf<int64_t> fbase;              // per device leaf cell
+  DevBuf<uint8_t> fmask;              // per device leaf cell
+  DevBuf<int32_t> canon;              // device leaf brick -> canonical leaf brick
+  DevBuf<int32_t> tbricks;            // device leaf bricks with a T-face
+  uint32_t n_tbricks = 0;
+  std::vector<Range> range;           // per level
+  uint32_t nlb = 0, nb = 0;
 };
 
 struct mfmg_coeffs {
   const mfmg_octree *tree = nullptr;
   std::unique_ptr<DeviceTopology> dt;
-  DevBuf<double> coef;  // nlb * 256, FP64 leaf coefficients
+  DevBuf<double> coef;  // nlb * 256, FP64 leaf coefficients (device order)
   DevBuf<double> tc;    // n_tplus * 48
   mfmg_bc bc{};
   int has_dirichlet = 0;
@@ -108,19 +120,31 @@ struct mfmg_hierarchy {
   const mfmg_coeffs *co = nullptr;
   mfmg_mg_params prm{};
   int L = 0, lc = 0;
-  DevBuf<double> coef64;  // nb * 256 (leaf part = assembled, inner = Algorithm 3)
-  DevBuf<float> coef32;   // nlb * 256 (mixed)
-  DevBuf<__half> coef16;  // (nb - nlb) * 256 (mixed)
-  DevBuf<float> tc32;     // mixed
-  DevBuf<uint64_t> act;   // nb
-  // work vectors
+  DevBuf<BrickMeta> meta;  // topology records with this hierarchy's activity masks
+  DevBuf<double> coef64;   // nb * 256 (leaf part = assembled, inner = Algorithm 3)
+  DevBuf<float> coef32;    // nlb * 256 (mixed)
+  DevBuf<__half> coef16;   // (nb - nlb) * 256 (mixed)
+  DevBuf<float> tc32;      // mixed
+  double n_active = 0;     // active leaf cells
+  // work vectors (device order)
   DevBuf<double> U64, B64, S64;  // FP64 cycle: nb*64, nb*64, (nb-nlb)*64
   DevBuf<float> U32, B32, S32;   // mixed cycle
-  DevBuf<double> r, pd, Ap;      // PCG (r aliases B64 in FP64 mode); pd is full-size
+  DevBuf<double> r;              // PCG residual (mixed; aliases B64 in FP64 mode)
+  DevBuf<double> x;              // PCG iterate (leaf size)
+  DevBuf<double> pd;             // search direction (full size: parent means of T bricks)
+  DevBuf<double> Ap;             // leaf size
   DevBuf<double> Xf;             // full-size scratch for operator applications
   DevBuf<double> partials;
   DevBuf<Scalars> S;
   DevBuf<double> hist;
+  // transposed cycle (allocated on first use): residual, solution, scratch
+  DevBuf<double> T64[5];          // RHO, Y, W (nb*64), SBAR, YS ((nb-nlb)*64)
+  DevBuf<float> T32[5];
+  DevBuf<double> rA;              // adjoint PCG residual
+  // face arrays for the per-face gradient (allocated on first use)
+  DevBuf<int64_t> f_owner, f_other;
+  DevBuf<int8_t> f_dir, f_kind, leaf_level;
+  DevBuf<uint64_t> canon_act;
   Scalars *hostS = nullptr;      // pinned
   ~mfmg_hierarchy() {
     if (hostS) (void)hipHostFree(hostS);
@@ -219,57 +243,88 @@ extern "C" void mfmg_destroy_octree(mfmg_octree *t) { delete t; }
 // --------------------------------------------------------------------------
 // device topology and coefficients
 // --------------------------------------------------------------------------
-static void upload_topology(const Topology &T, DeviceTopology &D, hipStream_t s) {
-  D.nbr.upload(T.nbr, s);
-  D.coord.upload(T.coord, s);
-  D.parent.upload(T.parent, s);
-  D.child.upload(T.child, s);
-  D.tplus.upload(T.tplus, s);
-  D.level.upload(T.level, s);
-  D.fbase.upload(T.cell_fbase, s);
-  D.fmask.upload(T.cell_fmask, s);
-  std::vector<uint32_t> flags(T.n_bricks, 0u);
-  for (int64_t b = 0; b < T.n_bricks; ++b)
+static void build_device_topology(const Topology &T, DeviceTopology &D, hipStream_t s) {
+  int64_t nlb = T.n_leaf_bricks, nb = T.n_bricks;
+  D.nlb = uint32_t(nlb);
+  D.nb = uint32_t(nb);
+  D.perm.assign(nb, -1);
+  std::vector<int32_t> order(nlb);
+  for (int64_t i = 0; i < nlb; ++i) order[i] = int32_t(i);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t a, int32_t b) { return T.level[a] > T.level[b]; });
+  std::vector<int32_t> canon(nlb);
+  for (int64_t i = 0; i < nlb; ++i) {
+    D.perm[order[i]] = int32_t(i);
+    canon[i] = order[i];
+  }
+  for (int64_t b = nlb; b < nb; ++b) D.perm[b] = int32_t(b);  // inner ids already level-major
+  int L = T.max_level;
+  D.range.assign(L + 1, Range{0, 0, 0, 0});
+  for (int64_t i = 0; i < nlb; ++i) {
+    Range &R = D.range[T.level[order[i]]];
+    if (R.n_leaf == 0) R.leaf_lo = uint32_t(i);
+    R.n_leaf++;
+  }
+  for (int l = kMinLevel; l <= L; ++l)
+    if (!T.level_inner[l].empty()) {
+      D.range[l].inner_lo = uint32_t(T.level_inner[l].front());
+      D.range[l].n_inner = uint32_t(T.level_inner[l].size());
+    }
+  D.meta_host.assign(nb, BrickMeta{});
+  std::vector<int32_t> child(8 * nb, -1);
+  for (int64_t b = 0; b < nb; ++b) {
+    BrickMeta &M = D.meta_host[D.perm[b]];
+    std::memset(&M, 0, sizeof(M));
+    M.flags = 0;
     for (int d = 0; d < 6; ++d) {
       int32_t n = T.nbr[6 * b + d];
-      if (n <= kCoarseBase) flags[b] |= 1u << d;
-      else if (n == kWall) flags[b] |= 1u << (16 + d);
-      else if (n >= T.n_leaf_bricks) flags[b] |= 1u << (8 + d);
+      if (n <= kCoarseBase) {
+        M.nbr[d] = encode_coarse(D.perm[decode_coarse(n)]);
+        M.flags |= 1u << d;
+      } else if (n == kWall) {
+        M.nbr[d] = kWall;
+        M.flags |= 1u << (16 + d);
+      } else {
+        M.nbr[d] = D.perm[n];
+        if (n >= nlb) M.flags |= 1u << (8 + d);
+      }
     }
-  D.flags.upload(flags, s);
-  std::vector<int32_t> lists;
-  int L = T.max_level;
-  D.all_off.assign(L + 1, 0);
-  D.all_n.assign(L + 1, 0);
-  D.in_off.assign(L + 1, 0);
-  D.in_n.assign(L + 1, 0);
-  for (int l = kMinLevel; l <= L; ++l) {
-    D.all_off[l] = int64_t(lists.size());
-    D.all_n[l] = int64_t(T.level_bricks[l].size());
-    lists.insert(lists.end(), T.level_bricks[l].begin(), T.level_bricks[l].end());
-    D.in_off[l] = int64_t(lists.size());
-    D.in_n[l] = int64_t(T.level_inner[l].size());
-    lists.insert(lists.end(), T.level_inner[l].begin(), T.level_inner[l].end());
+    M.parent = T.parent[b] >= 0 ? D.perm[T.parent[b]] : -1;
+    M.tplus = b < nlb ? T.tplus[b] : -1;
+    for (int a = 0; a < 3; ++a) M.coord[a] = T.coord[3 * b + a];
+    M.level = T.level[b];
+    for (int o = 0; o < 8; ++o) {
+      int32_t c = T.child[8 * b + o];
+      child[8 * int64_t(D.perm[b]) + o] = c >= 0 ? D.perm[c] : -1;
+    }
   }
-  std::vector<int32_t> leaf(T.n_leaf_bricks);
-  for (int64_t i = 0; i < T.n_leaf_bricks; ++i) leaf[i] = int32_t(i);
-  D.lists.upload(lists, s);
-  D.leaf_list.upload(leaf, s);
-  D.act.alloc(T.n_bricks);
+  std::vector<int64_t> fbase(nlb * kCells);
+  std::vector<uint8_t> fmask(nlb * kCells);
+  for (int64_t b = 0; b < nlb; ++b)
+    for (int m = 0; m < kCells; ++m) {
+      fbase[int64_t(D.perm[b]) * kCells + m] = T.cell_fbase[b * kCells + m];
+      fmask[int64_t(D.perm[b]) * kCells + m] = T.cell_fmask[b * kCells + m];
+    }
+  std::vector<int32_t> tb;
+  for (int64_t b = 0; b < nlb; ++b)
+    if (D.meta_host[b].flags & kFlagT) tb.push_back(int32_t(b));
+  D.n_tbricks = uint32_t(tb.size());
+  if (tb.empty()) tb.push_back(0);
+  D.tbricks.upload(tb, s);
+  D.meta.upload(D.meta_host, s);
+  D.child.upload(child, s);
+  D.fbase.upload(fbase, s);
+  D.fmask.upload(fmask, s);
+  D.canon.upload(canon, s);
   HIP_CHECK(hipStreamSynchronize(s));
 }
 
-static Topo make_topo(const Topology &T, const DeviceTopology &D, const uint64_t *act) {
+static Topo make_topo(const DeviceTopology &D, const BrickMeta *meta) {
   Topo t;
-  t.nlb = T.n_leaf_bricks;
-  t.nb = T.n_bricks;
-  t.nbr = D.nbr.p;
-  t.coord = D.coord.p;
-  t.parent = D.parent.p;
+  t.nlb = D.nlb;
+  t.nb = D.nb;
+  t.meta = meta;
   t.child = D.child.p;
-  t.tplus = D.tplus.p;
-  t.act = act;
-  t.flags = D.flags.p;
   return t;
 }
 
@@ -290,15 +345,14 @@ extern "C" mfmg_status mfmg_assemble_coeffs(const mfmg_octree *tree, const doubl
     co->bc = *bc;
     for (int d = 0; d < 6; ++d) co->has_dirichlet |= bc->bc[d] == MFMG_DIRICHLET;
     co->dt.reset(new DeviceTopology());
-    upload_topology(T, *co->dt, s);
+    build_device_topology(T, *co->dt, s);
     co->coef.alloc(size_t(T.n_leaf_bricks) * 256);
     co->tc.alloc(size_t(T.n_tplus) * 48 + 1);
     AssembleArgs A;
-    A.T = make_topo(T, *co->dt, co->dt->act.p);
+    A.T = make_topo(*co->dt, co->dt->meta.p);
     A.fbase = co->dt->fbase.p;
     A.fmask = co->dt->fmask.p;
     A.beta = face_beta;
-    A.blevel = co->dt->level.p;
     for (int d = 0; d < 6; ++d) A.bc[d] = bc->bc[d];
     A.theta = bc->theta;
     A.coef = co->coef.p;
@@ -308,28 +362,35 @@ extern "C" mfmg_status mfmg_assemble_coeffs(const mfmg_octree *tree, const doubl
     HIP_CHECK(hipStreamSynchronize(s));
     *out = co.release();
   } catch (const HipError &e) {
-    return fail(e.e == hipErrorOutOfMemory ? MFMG_ERR_OOM : MFMG_ERR_HIP,
-                std::string(e.what) + ": " + hipGetErrorString(e.e));
+    return hip_fail(e);
   } catch (const std::bad_alloc &) {
     return fail(MFMG_ERR_OOM, "host allocation failed");
   }
   return MFMG_OK;
 }
 
+// leaf coefficients (device order) -> [c | kx | ky | kz], each canonical
+__global__ void k_coef_to_canonical(const double *coef, const int32_t *canon, uint32_t nlb,
+                                    double *out) {
+  uint32_t b = blockIdx.x * kWavesPerBlock + wave_id();
+  int m = threadIdx.x & (kWave - 1);
+  if (b >= nlb) return;
+  uint64_t N = uint64_t(nlb) * 64u;
+  for (int comp = 0; comp < 4; ++comp)
+    out[comp * N + uint64_t(canon[b]) * 64u + m] = coef[b * 256u + comp * 64 + m];
+}
+
 extern "C" mfmg_status mfmg_coeffs_leaf(const mfmg_coeffs *co, double *out, void *stream) {
   if (!co || !out) return fail(MFMG_ERR_INVALID_ARG, "NULL argument");
   hipStream_t s = (hipStream_t)stream;
-  const Topology &T = co->tree->topo;
-  int64_t N = T.n_leaves();
   try {
-    for (int comp = 0; comp < 4; ++comp)
-      HIP_CHECK(hipMemcpy2DAsync(out + comp * N + 0, 64 * sizeof(double),
-                                 co->coef.p + comp * 64, 256 * sizeof(double),
-                                 64 * sizeof(double), size_t(T.n_leaf_bricks),
-                                 hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_coef_to_canonical, dim3(grid_for(co->dt->nlb)), dim3(kBlock), 0, s,
+                       (const double *)co->coef.p, (const int32_t *)co->dt->canon.p,
+                       co->dt->nlb, out);
+    HIP_CHECK(hipGetLastError());
     HIP_CHECK(hipStreamSynchronize(s));
   } catch (const HipError &e) {
-    return fail(MFMG_ERR_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    return hip_fail(e);
   }
   return MFMG_OK;
 }
@@ -339,33 +400,6 @@ extern "C" void mfmg_destroy_coeffs(mfmg_coeffs *co) { delete co; }
 // --------------------------------------------------------------------------
 // hierarchy
 // --------------------------------------------------------------------------
-template <class V, class CL, class CI>
-static LevelArgs<V, CL, CI> level_args(const mfmg_hierarchy *h, int l, bool inner_only,
-                                       const CL *leafc, const CI *innerc, const CL *tc,
-                                       V *U, V *B, V *Ust, V iscale, const int *done) {
-  const Topology &T = h->co->tree->topo;
-  const DeviceTopology &D = *h->co->dt;
-  LevelArgs<V, CL, CI> A;
-  A.T = make_topo(T, D, h->act.p);
-  A.cf.leaf = leafc;
-  A.cf.inner = innerc;
-  A.cf.tc = tc;
-  A.cf.nlb = T.n_leaf_bricks;
-  A.cf.iscale = iscale;
-  A.U = U;
-  A.B = B;
-  A.Ustar = Ust;
-  if (inner_only) {
-    A.list = D.lists.p + D.in_off[l];
-    A.n = D.in_n[l];
-  } else {
-    A.list = D.lists.p + D.all_off[l];
-    A.n = D.all_n[l];
-  }
-  A.done = done;
-  return A;
-}
-
 extern "C" mfmg_status mfmg_build_hierarchy(const mfmg_coeffs *co, const mfmg_mg_params *prm,
                                             void *stream, mfmg_hierarchy **out) {
   if (!co || !prm || !out) return fail(MFMG_ERR_INVALID_ARG, "NULL argument");
@@ -383,29 +417,28 @@ extern "C" mfmg_status mfmg_build_hierarchy(const mfmg_coeffs *co, const mfmg_mg
   hipStream_t s = (hipStream_t)stream;
   try {
     std::unique_ptr<mfmg_hierarchy> h(new mfmg_hierarchy());
+    const DeviceTopology &D = *co->dt;
     h->co = co;
     h->prm = *prm;
     h->lc = prm->coarsest_level;
     h->L = 0;
     for (int l = kMinLevel; l <= T.max_level; ++l)
-      if (!co->dt->all_n.empty() && co->dt->all_n[l] > 0) h->L = l;
-    const DeviceTopology &D = *co->dt;
-    int64_t nb = T.n_bricks, nlb = T.n_leaf_bricks, N = T.n_leaves();
+      if (D.range[l].n() > 0) h->L = l;
+    int64_t nb = D.nb, nlb = D.nlb, N = nlb * 64;
+    h->meta.upload(D.meta_host, s);
     h->coef64.alloc(size_t(nb) * 256);
-    h->act.alloc(size_t(nb));
     HIP_CHECK(hipMemcpyAsync(h->coef64.p, co->coef.p, size_t(nlb) * 256 * sizeof(double),
                              hipMemcpyDeviceToDevice, s));
     hipLaunchKernelGGL(k_active_mask, dim3(grid_for(nlb)), dim3(kBlock), 0, s,
-                       (const double *)h->coef64.p, (const int32_t *)nullptr, nlb, h->act.p);
-    Topo topo = make_topo(T, D, h->act.p);
+                       (const double *)h->coef64.p, 0u, uint32_t(nlb), h->meta.p);
+    Topo topo = make_topo(D, h->meta.p);
     for (int l = T.max_level - 1; l >= kMinLevel; --l) {
-      int64_t n = D.in_n[l];
-      if (n == 0) continue;
-      const int32_t *list = D.lists.p + D.in_off[l];
-      hipLaunchKernelGGL(k_coarsen, dim3(grid_for(n)), dim3(kBlock), 0, s, list, n, topo,
-                         h->coef64.p, prm->alpha);
-      hipLaunchKernelGGL(k_active_mask, dim3(grid_for(n)), dim3(kBlock), 0, s,
-                         (const double *)h->coef64.p, list, n, h->act.p);
+      const Range &R = D.range[l];
+      if (R.n_inner == 0) continue;
+      hipLaunchKernelGGL(k_coarsen, dim3(grid_for(R.n_inner)), dim3(kBlock), 0, s, R.inner_lo,
+                         R.n_inner, topo, h->coef64.p, prm->alpha);
+      hipLaunchKernelGGL(k_active_mask, dim3(grid_for(R.n_inner)), dim3(kBlock), 0, s,
+                         (const double *)h->coef64.p, R.inner_lo, R.n_inner, h->meta.p);
     }
     HIP_CHECK(hipGetLastError());
     if (prm->precision == MFMG_MIXED) {
@@ -418,8 +451,7 @@ extern "C" mfmg_status mfmg_build_hierarchy(const mfmg_coeffs *co, const mfmg_mg
                          0, s, (const double *)co->tc.p, h->tc32.p, int64_t(co->tc.n));
       if (nb > nlb)
         hipLaunchKernelGGL(k_convert_inner, dim3(grid_for(nb - nlb)), dim3(kBlock), 0, s,
-                           (const double *)h->coef64.p, (const int8_t *)D.level.p, nlb, nb,
-                           h->coef16.p);
+                           (const double *)h->coef64.p, topo, h->coef16.p);
       h->U32.alloc(size_t(nb) * 64);
       h->B32.alloc(size_t(nb) * 64);
       h->S32.alloc(size_t(nb - nlb) * 64 + 1);
@@ -429,19 +461,26 @@ extern "C" mfmg_status mfmg_build_hierarchy(const mfmg_coeffs *co, const mfmg_mg
       h->B64.alloc(size_t(nb) * 64);
       h->S64.alloc(size_t(nb - nlb) * 64 + 1);
     }
+    h->x.alloc(size_t(N));
     h->pd.alloc(size_t(nb) * 64);
     h->Xf.alloc(size_t(nb) * 64);
     h->Ap.alloc(size_t(N));
-    h->partials.alloc(4096);
+    h->partials.alloc(std::max<int64_t>(kMaxReduceBlocks, grid_for(nlb)));
     h->S.alloc(1);
     HIP_CHECK(hipMemsetAsync(h->S.p, 0, sizeof(Scalars), s));
     HIP_CHECK(hipHostMalloc(&h->hostS, sizeof(Scalars), hipHostMallocDefault));
+    // active leaf count (for the null-space mean)
+    std::vector<BrickMeta> mh(nlb);
+    HIP_CHECK(hipMemcpyAsync(mh.data(), h->meta.p, size_t(nlb) * sizeof(BrickMeta),
+                             hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipGetLastError());
     HIP_CHECK(hipStreamSynchronize(s));
+    int64_t na = 0;
+    for (const BrickMeta &M : mh) na += __builtin_popcount(M.act[0]) + __builtin_popcount(M.act[1]);
+    h->n_active = double(na);
     *out = h.release();
   } catch (const HipError &e) {
-    return fail(e.e == hipErrorOutOfMemory ? MFMG_ERR_OOM : MFMG_ERR_HIP,
-                std::string(e.what) + ": " + hipGetErrorString(e.e));
+    return hip_fail(e);
   } catch (const std::bad_alloc &) {
     return fail(MFMG_ERR_OOM, "host allocation failed");
   }
@@ -474,11 +513,12 @@ extern "C" mfmg_status mfmg_hierarchy_level_coeffs(const mfmg_hierarchy *h, int 
   try {
     const auto &lst = T.level_bricks[level];
     for (size_t i = 0; i < lst.size(); ++i)
-      HIP_CHECK(hipMemcpyAsync(out + i * 256, h->coef64.p + int64_t(lst[i]) * 256,
+      HIP_CHECK(hipMemcpyAsync(out + i * 256,
+                               h->coef64.p + int64_t(h->co->dt->perm[lst[i]]) * 256,
                                256 * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIP_CHECK(hipStreamSynchronize(s));
   } catch (const HipError &e) {
-    return fail(MFMG_ERR_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    return hip_fail(e);
   }
   return MFMG_OK;
 }
@@ -504,24 +544,40 @@ struct Cycle {
     return std::is_same<CI, __half>::value ? V(std::ldexp(1.0, -l)) : V(1);
   }
   LevelArgs<V, CL, CI> args(int l, bool inner_only) const {
-    return level_args<V, CL, CI>(h, l, inner_only, leafc, innerc, tc, U, B, Ust, iscale(l),
-                                 done);
+    const DeviceTopology &D = *h->co->dt;
+    LevelArgs<V, CL, CI> A;
+    A.T = make_topo(D, h->meta.p);
+    A.cf.leaf = leafc;
+    A.cf.inner = innerc;
+    A.cf.tc = tc;
+    A.cf.nlb = D.nlb;
+    A.cf.iscale = iscale(l);
+    A.U = U;
+    A.B = B;
+    A.Ustar = Ust;
+    A.R = D.range[l];
+    if (inner_only) {
+      A.R.n_leaf = 0;
+      A.R.leaf_lo = 0;
+    }
+    A.done = done;
+    return A;
   }
 
   void smooth(int l, int first, int nu) const {
     auto A = args(l, false);
-    if (A.n == 0) return;
+    if (A.R.n() == 0) return;
     for (int it = 0; it < nu; ++it)
       for (int c = 0; c < 2; ++c)
-        hipLaunchKernelGGL((k_smooth<V, CL, CI>), dim3(grid_for(A.n)), dim3(kBlock), 0, s, A,
-                           c == 0 ? first : 1 - first);
+        hipLaunchKernelGGL((k_smooth<V, CL, CI>), dim3(grid_for(A.R.n())), dim3(kBlock), 0, s,
+                           A, c == 0 ? first : 1 - first);
   }
 
   void fas(int l) const {
     const mfmg_mg_params &p = h->prm;
     if (l == h->lc) {
       auto A = args(l, false);
-      int threads = int(std::min<int64_t>(16, A.n)) * kWave;
+      int threads = int(std::min<int64_t>(16, A.R.n())) * kWave;
       hipLaunchKernelGGL((k_coarsest<V, CL, CI>), dim3(1), dim3(threads), 0, s, A,
                          p.nu_coarse);
       return;
@@ -529,19 +585,19 @@ struct Cycle {
     smooth(l, 0, p.nu_pre);
     auto A = args(l, false);
     V scale = V(p.beta_mg / p.alpha);
-    hipLaunchKernelGGL((k_restrict<V, CL, CI>), dim3(grid_for(A.n)), dim3(kBlock), 0, s, A,
+    hipLaunchKernelGGL((k_restrict<V, CL, CI>), dim3(grid_for(A.R.n())), dim3(kBlock), 0, s, A,
                        scale);
     auto C = args(l - 1, true);
-    if (C.n)
-      hipLaunchKernelGGL((k_fas_rhs<V, CL, CI>), dim3(grid_for(C.n)), dim3(kBlock), 0, s, C);
+    if (C.R.n())
+      hipLaunchKernelGGL((k_fas_rhs<V, CL, CI>), dim3(grid_for(C.R.n())), dim3(kBlock), 0, s,
+                         C);
     for (int k = 0; k < p.mu; ++k) fas(l - 1);
-    hipLaunchKernelGGL((k_prolong<V, CL, CI>), dim3(grid_for(A.n)), dim3(kBlock), 0, s, A);
+    hipLaunchKernelGGL((k_prolong<V, CL, CI>), dim3(grid_for(A.R.n())), dim3(kBlock), 0, s, A);
     smooth(l, 1, p.nu_post);
   }
 
   void run() const {
-    const Topology &T = h->co->tree->topo;
-    int64_t N = T.n_leaves();
+    int64_t N = int64_t(h->co->dt->nlb) * 64;
     hipLaunchKernelGGL((k_fill<V>), dim3(grid_elems(N, 256)), dim3(256), 0, s, U, N, V(0));
     fas(h->L);
   }
@@ -553,256 +609,167 @@ void run_cycle(const mfmg_hierarchy *h, hipStream_t s, const int *done) {
                                   h->U32.p, h->B32.p, h->S32.p, done, s};
     c.run();
   } else {
-    Cycle<double, double, double> c{h, h->coef64.p, h->coef64.p + 0, h->co->tc.p,
-                                    h->U64.p, h->B64.p, h->S64.p, done, s};
-    // FP64 inner coefficients live in the same array, after the leaf bricks
-    c.innerc = h->coef64.p + h->co->tree->topo.n_leaf_bricks * 256;
+    // FP64 inner coefficients directly follow the leaf ones in coef64
+    Cycle<double, double, double> c{h, h->coef64.p, h->coef64.p + int64_t(h->co->dt->nlb) * 256,
+                                    h->co->tc.p, h->U64.p, h->B64.p, h->S64.p, done, s};
     c.run();
   }
 }
 
-}  // namespace
+// Transpose of the cycle (exact adjoint of run_cycle's linear map), in
+// residual form: RHO leaf part = input, output = Y leaf part.
+template <class V, class CL, class CI>
+struct CycleT {
+  const mfmg_hierarchy *h;
+  const CL *leafc;
+  const CI *innerc;
+  const CL *tc;
+  V *RHO, *Y, *W, *SBAR, *YS;
+  hipStream_t s;
 
-// --------------------------------------------------------------------------
-// PCG kernels
-// --------------------------------------------------------------------------
-namespace mfmg {
-
-struct PcgArgs {
-  Topo T;
-  const double *C;   // FP64 coefficients, leaf bricks first
-  const double *TC;  // FP64 plus-side T coefficients
-  Scalars *S;
-  double *partials;
-  double *hist;
+  V iscale(int l) const {
+    return std::is_same<CI, __half>::value ? V(std::ldexp(1.0, -l)) : V(1);
+  }
+  LevelArgsT<V, CL, CI> args(int l, int part) const {  // part: 0 all, 1 leaf only
+    const DeviceTopology &D = *h->co->dt;
+    LevelArgsT<V, CL, CI> A;
+    A.T = make_topo(D, h->meta.p);
+    A.cf.leaf = leafc;
+    A.cf.inner = innerc;
+    A.cf.tc = tc;
+    A.cf.nlb = D.nlb;
+    A.cf.iscale = iscale(l);
+    A.RHO = RHO;
+    A.Y = Y;
+    A.W = W;
+    A.SBAR = SBAR;
+    A.YS = YS;
+    A.R = D.range[l];
+    if (part == 1) {
+      A.R.n_inner = 0;
+      A.R.inner_lo = 0;
+    }
+    A.bscale = V(h->prm.beta_mg / h->prm.alpha);
+    return A;
+  }
+  void launch_apply(int l) const {
+    auto A = args(l, 0);
+    hipLaunchKernelGGL((k_T_apply<V, CL, CI>), dim3(grid_for(A.R.n())), dim3(kBlock), 0, s, A);
+    if (l > h->lc) {
+      auto C = args(l - 1, 1);
+      if (C.R.n())
+        hipLaunchKernelGGL((k_T_coupling<V, CL, CI>), dim3(grid_for(C.R.n())), dim3(kBlock), 0,
+                           s, C);
+    }
+  }
+  // transpose of smooth(l, (c0, 1 - c0), nu): colours in reversed order
+  void smooth_T(int l, int first, int nu) const {
+    auto A = args(l, 0);
+    if (A.R.n() == 0) return;
+    for (int it = 0; it < nu; ++it)
+      for (int c = 0; c < 2; ++c) {
+        hipLaunchKernelGGL((k_T_sweep_w<V, CL, CI>), dim3(grid_for(A.R.n())), dim3(kBlock), 0,
+                           s, A, c == 0 ? first : 1 - first);
+        launch_apply(l);
+      }
+  }
+  void fas_T(int l) const {
+    const mfmg_mg_params &p = h->prm;
+    if (l == h->lc) {
+      auto A = args(l, 0);
+      int threads = int(std::min<int64_t>(16, A.R.n())) * kWave;
+      hipLaunchKernelGGL((k_T_coarsest<V, CL, CI>), dim3(1), dim3(threads), 0, s, A,
+                         p.nu_coarse);
+      return;
+    }
+    smooth_T(l, 0, p.nu_post);  // forward post-smoothing is (B,R)^nu
+    auto A = args(l, 0);
+    hipLaunchKernelGGL((k_T_restrict<V, CL, CI>), dim3(grid_for(A.R.n())), dim3(kBlock), 0, s,
+                       A);
+    for (int k = 0; k < p.mu; ++k) fas_T(l - 1);
+    auto C = args(l - 1, 0);
+    hipLaunchKernelGGL((k_T_coarse<V, CL, CI>), dim3(grid_for(C.R.n())), dim3(kBlock), 0, s, C);
+    hipLaunchKernelGGL((k_T_fas<V, CL, CI>), dim3(grid_for(C.R.n())), dim3(kBlock), 0, s, C);
+    hipLaunchKernelGGL((k_T_prolong<V, CL, CI>), dim3(grid_for(A.R.n())), dim3(kBlock), 0, s,
+                       A);
+    launch_apply(l);
+    smooth_T(l, 1, p.nu_pre);  // forward pre-smoothing is (R,B)^nu
+  }
+  // input: an FP64 leaf vector in device order
+  void run(const double *in) const {
+    const DeviceTopology &D = *h->co->dt;
+    int64_t nb64 = int64_t(D.nb) * 64, N = int64_t(D.nlb) * 64;
+    hipLaunchKernelGGL((k_fill<V>), dim3(grid_elems(nb64, 256)), dim3(256), 0, s, Y, nb64, V(0));
+    hipLaunchKernelGGL((k_fill<V>), dim3(grid_elems(nb64 - N, 256)), dim3(256), 0, s, RHO + N,
+                       nb64 - N, V(0));
+    hipLaunchKernelGGL((k_T_load<V>), dim3(grid_elems(N, 256)), dim3(256), 0, s, in, RHO, N);
+    fas_T(h->L);
+  }
 };
 
-__device__ __forceinline__ void leaf_cell(const PcgArgs &P, uint32_t b, int m, double &c,
-                                          double &k0, double &k1, double &k2) {
-  const double *cf = P.C + b * 256u;
-  c = cf[m];
-  k0 = cf[64 + m];
-  k1 = cf[128 + m];
-  k2 = cf[192 + m];
-}
-
-#define BRICK_LOOP(P)                                                               \
-  int m = threadIdx.x & (kWave - 1);                                                \
-  for (uint32_t b = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;              \
-       b < uint32_t((P).T.nlb); b += gridDim.x * kWavesPerBlock)
-
-// r = rhs on active cells, x = 0, ||r||^2
 template <class V>
-__global__ void __launch_bounds__(kBlock) k_pcg_init(PcgArgs P, const double *rhs, double *r,
-                                                     V *r_low, double *x, double rtol) {
-  double part = 0.0;
-  BRICK_LOOP(P) {
-    bool act = (P.T.act[b] >> m) & 1ull;
-    double v = act ? rhs[b * 64u + m] : 0.0;
-    r[b * 64u + m] = v;
-    if (r_low) r_low[b * 64u + m] = V(v);
-    x[b * 64u + m] = 0.0;
-    part += v * v;
-  }
-  Scalars *S = P.S;
-  block_reduce_finish(part, P.partials, &S->ticket[0], [&](double tot) {
-    S->rr0 = tot;
-    S->rr = tot;
-    S->tol2 = rtol * rtol * tot;
-    S->iters = 0;
-    S->status = 0;
-    S->done = (tot == 0.0) || !(tot < INFINITY);
-    if (!(tot < INFINITY)) S->status = -5;
-    S->rz = 0.0;
-    P.hist[0] = tot > 0.0 ? 1.0 : 0.0;
-  });
+void alloc_transpose(const mfmg_hierarchy *hc, DevBuf<V> (&T)[5]) {
+  if (T[0].p) return;
+  int64_t nb = hc->co->dt->nb, nlb = hc->co->dt->nlb;
+  for (int i = 0; i < 3; ++i) T[i].alloc(size_t(nb) * 64);
+  for (int i = 3; i < 5; ++i) T[i].alloc(size_t(nb - nlb) * 64 + 1);
 }
 
-// (r, z) and beta = (r, z) / (r, z)_old (beta = 0 on the first call)
-template <class V>
-__global__ void __launch_bounds__(kBlock) k_pcg_rz(PcgArgs P, const double *r, const V *z,
-                                                   int first) {
-  if (P.S->done) return;
-  double part = 0.0;
-  BRICK_LOOP(P) { part += r[b * 64u + m] * double(z[b * 64u + m]); }
-  Scalars *S = P.S;
-  block_reduce_finish(part, P.partials, &S->ticket[1], [&](double tot) {
-    if (!(tot > 0.0) || !(tot < INFINITY)) {
-      S->status = -5;
-      S->done = 1;
-      return;
-    }
-    S->beta = first ? 0.0 : tot / S->rz;
-    S->rz = tot;
-  });
-}
-
-// p = z + beta p (p = z on the first call)
-template <class V>
-__global__ void __launch_bounds__(kBlock) k_pcg_p(PcgArgs P, const V *z, double *p, int first) {
-  if (P.S->done) return;
-  double beta = P.S->beta;
-  BRICK_LOOP(P) {
-    uint64_t amask = P.T.act[b];
-    bool act = (amask >> m) & 1ull;
-    double v = double(z[b * 64u + m]);
-    if (!first) v = v + beta * p[b * 64u + m];
-    v = act ? v : 0.0;
-    p[b * 64u + m] = v;
-    if (P.T.flags[b] & kFlagT) average_up(P.T, p, b, m, v, amask);
+// z = M^T r: r, z FP64 leaf vectors in device order; returns the z buffer
+// (the Y leaf part, of the cycle's value type)
+void run_cycle_T(mfmg_hierarchy *h, const double *r, hipStream_t s) {
+  if (h->prm.precision == MFMG_MIXED) {
+    alloc_transpose(h, h->T32);
+    CycleT<float, float, __half> c{h, h->coef32.p, h->coef16.p, h->tc32.p, h->T32[0].p,
+                                   h->T32[1].p, h->T32[2].p, h->T32[3].p, h->T32[4].p, s};
+    c.run(r);
+  } else {
+    alloc_transpose(h, h->T64);
+    CycleT<double, double, double> c{h, h->coef64.p,
+                                     h->coef64.p + int64_t(h->co->dt->nlb) * 256,
+                                     h->co->tc.p, h->T64[0].p, h->T64[1].p, h->T64[2].p,
+                                     h->T64[3].p, h->T64[4].p, s};
+    c.run(r);
   }
 }
 
-// Ap = A p (composite operator) and alpha = (r, z) / (p, Ap)
-__global__ void __launch_bounds__(kBlock) k_pcg_Ap(PcgArgs P, const double *p, double *Ap) {
-  if (P.S->done) return;
-  double part = 0.0;
-  BRICK_LOOP(P) {
-    double c, k0, k1, k2;
-    leaf_cell(P, b, m, c, k0, k1, k2);
-    double u = p[b * 64u + m];
-    int32_t nb6[6];
-    load_nbr(P.T, b, nb6);
-    double y = composite_Au(P.T, P.C, P.TC, p, b, m, u, c, k0, k1, k2, P.T.act[b],
-                            P.T.flags[b], nb6);
-    Ap[b * 64u + m] = y;
-    part += u * y;
-  }
-  Scalars *S = P.S;
-  block_reduce_finish(part, P.partials, &S->ticket[2], [&](double tot) {
-    S->pAp = tot;
-    if (!(tot > 0.0) || !(tot < INFINITY)) {
-      S->status = -5;
-      S->done = 1;
-      return;
-    }
-    S->alpha = S->rz / tot;
-  });
-}
-
-// x += alpha p, r -= alpha Ap, ||r||^2, stop test
-template <class V>
-__global__ void __launch_bounds__(kBlock) k_pcg_update(PcgArgs P, double *x, double *r,
-                                                       V *r_low, const double *p,
-                                                       const double *Ap) {
-  if (P.S->done) return;
-  double alpha = P.S->alpha;
-  double part = 0.0;
-  BRICK_LOOP(P) {
-    uint32_t i = b * 64u + m;
-    x[i] = x[i] + alpha * p[i];
-    double v = r[i] - alpha * Ap[i];
-    r[i] = v;
-    if (r_low) r_low[i] = V(v);
-    part += v * v;
-  }
-  Scalars *S = P.S;
-  block_reduce_finish(part, P.partials, &S->ticket[3], [&](double tot) {
-    S->rr = tot;
-    S->iters += 1;
-    P.hist[S->iters] = S->rr0 > 0.0 ? sqrt(tot / S->rr0) : 0.0;
-    if (!(tot < INFINITY)) {
-      S->status = -5;
-      S->done = 1;
-    } else if (tot <= S->tol2) {
-      S->done = 1;
-    }
-  });
-}
-
-// copy a leaf vector into the leaf part of a full-size vector and write the
-// parent means that the composite operator reads for inner neighbours
-__global__ void __launch_bounds__(kBlock) k_full(PcgArgs P, const double *x, double *X) {
-  BRICK_LOOP(P) {
-    uint64_t amask = P.T.act[b];
-    double v = ((amask >> m) & 1ull) ? x[b * 64u + m] : 0.0;
-    X[b * 64u + m] = v;
-    if (P.T.flags[b] & kFlagT) average_up(P.T, X, b, m, v, amask);
-  }
-}
-
-// y = A X (X full-size, from k_full) or y = A^T x (x a leaf vector)
-template <bool TRANS>
-__global__ void __launch_bounds__(kBlock) k_apply(PcgArgs P, const double *x, double *y) {
-  BRICK_LOOP(P) {
-    double c, k0, k1, k2;
-    leaf_cell(P, b, m, c, k0, k1, k2);
-    int32_t nb6[6];
-    load_nbr(P.T, b, nb6);
-    if (TRANS)
-      y[b * 64u + m] = composite_AuT(P.T, P.C, P.TC, x, b, m, x[b * 64u + m], c, k0, k1, k2,
-                                    P.T.act[b], P.T.flags[b], nb6);
-    else
-      y[b * 64u + m] = composite_Au(P.T, P.C, P.TC, x, b, m, x[b * 64u + m], c, k0, k1, k2,
-                                   P.T.act[b], P.T.flags[b], nb6);
-  }
-}
-
-// ||rhs - A x||^2 over active cells
-__global__ void __launch_bounds__(kBlock) k_true_resid(PcgArgs P, const double *rhs,
-                                                       const double *x) {
-  double part = 0.0;
-  BRICK_LOOP(P) {
-    double c, k0, k1, k2;
-    leaf_cell(P, b, m, c, k0, k1, k2);
-    int32_t nb6[6];
-    load_nbr(P.T, b, nb6);
-    double y = composite_Au(P.T, P.C, P.TC, x, b, m, x[b * 64u + m], c, k0, k1, k2,
-                            P.T.act[b], P.T.flags[b], nb6);
-    bool act = (P.T.act[b] >> m) & 1ull;
-    double t = act ? rhs[b * 64u + m] - y : 0.0;
-    part += t * t;
-  }
-  Scalars *S = P.S;
-  block_reduce_finish(part, P.partials, &S->ticket[0], [&](double tot) { S->tr = tot; });
-}
-
-// copy a leaf vector into the low-precision right-hand side of the cycle
-template <class V>
-__global__ void k_to_low(const double *src, V *dst, int64_t n) {
-  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = V(src[i]);
-}
-template <class V>
-__global__ void k_from_low(const V *src, double *dst, const uint64_t *act, int64_t n) {
-  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = ((act[i >> 6] >> (i & 63)) & 1ull) ? double(src[i]) : 0.0;
-}
-
-}  // namespace mfmg
-
-static PcgArgs pcg_args(mfmg_hierarchy *h) {
-  const Topology &T = h->co->tree->topo;
+PcgArgs pcg_args(mfmg_hierarchy *h) {
   PcgArgs P;
-  P.T = make_topo(T, *h->co->dt, h->act.p);
+  P.T = make_topo(*h->co->dt, h->meta.p);
   P.C = h->coef64.p;
   P.TC = h->co->tc.p;
+  P.canon = h->co->dt->canon.p;
   P.S = h->S.p;
   P.partials = h->partials.p;
   P.hist = h->hist.p;
   return P;
 }
 
+}  // namespace
+
+// --------------------------------------------------------------------------
+// component entry points
+// --------------------------------------------------------------------------
 extern "C" mfmg_status mfmg_apply_operator(mfmg_hierarchy *h, const double *x, double *y,
                                            int transpose, void *stream) {
   if (!h || !x || !y) return fail(MFMG_ERR_INVALID_ARG, "NULL argument");
   hipStream_t s = (hipStream_t)stream;
-  const Topology &T = h->co->tree->topo;
+  unsigned G = grid_for(h->co->dt->nlb);
   try {
     PcgArgs P = pcg_args(h);
-    if (transpose) {
-      hipLaunchKernelGGL(k_apply<true>, dim3(grid_for(T.n_leaf_bricks)), dim3(kBlock), 0, s, P,
-                         x, y);
-    } else {
-      hipLaunchKernelGGL(k_full, dim3(grid_for(T.n_leaf_bricks)), dim3(kBlock), 0, s, P, x,
-                         h->Xf.p);
-      hipLaunchKernelGGL(k_apply<false>, dim3(grid_for(T.n_leaf_bricks)), dim3(kBlock), 0, s,
-                         P, (const double *)h->Xf.p, y);
-    }
+    hipLaunchKernelGGL(k_full, dim3(G), dim3(kBlock), 0, s, P, x, h->Xf.p, 1);
+    if (transpose)
+      hipLaunchKernelGGL(k_apply<true>, dim3(G), dim3(kBlock), 0, s, P, (const double *)h->Xf.p,
+                         h->Ap.p);
+    else
+      hipLaunchKernelGGL(k_apply<false>, dim3(G), dim3(kBlock), 0, s, P,
+                         (const double *)h->Xf.p, h->Ap.p);
+    hipLaunchKernelGGL(k_to_canonical<double>, dim3(G), dim3(kBlock), 0, s, P,
+                       (const double *)h->Ap.p, y);
     HIP_CHECK(hipGetLastError());
     HIP_CHECK(hipStreamSynchronize(s));
   } catch (const HipError &e) {
-    return fail(MFMG_ERR_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    return hip_fail(e);
   }
   return MFMG_OK;
 }
@@ -810,61 +777,133 @@ extern "C" mfmg_status mfmg_apply_operator(mfmg_hierarchy *h, const double *x, d
 extern "C" mfmg_status mfmg_apply_precond(mfmg_hierarchy *h, const double *r, double *z,
                                           int transpose, void *stream) {
   if (!h || !r || !z) return fail(MFMG_ERR_INVALID_ARG, "NULL argument");
-  if (transpose) return fail(MFMG_ERR_INVALID_ARG, "transposed cycle not available");
   hipStream_t s = (hipStream_t)stream;
-  const Topology &T = h->co->tree->topo;
-  int64_t N = T.n_leaves();
+  unsigned G = grid_for(h->co->dt->nlb);
   try {
-    if (h->prm.precision == MFMG_MIXED) {
-      hipLaunchKernelGGL(k_to_low<float>, dim3(grid_elems(N, 256)), dim3(256), 0, s, r,
-                         h->B32.p, N);
+    PcgArgs P = pcg_args(h);
+    if (transpose) {
+      if (!h->rA.p) h->rA.alloc(size_t(h->co->dt->nlb) * 64);
+      hipLaunchKernelGGL(k_from_canonical<double>, dim3(G), dim3(kBlock), 0, s, P, r, h->rA.p);
+      run_cycle_T(h, h->rA.p, s);
+      if (h->prm.precision == MFMG_MIXED)
+        hipLaunchKernelGGL(k_to_canonical<float>, dim3(G), dim3(kBlock), 0, s, P,
+                           (const float *)h->T32[1].p, z);
+      else
+        hipLaunchKernelGGL(k_to_canonical<double>, dim3(G), dim3(kBlock), 0, s, P,
+                           (const double *)h->T64[1].p, z);
+    } else if (h->prm.precision == MFMG_MIXED) {
+      hipLaunchKernelGGL(k_from_canonical<float>, dim3(G), dim3(kBlock), 0, s, P, r, h->B32.p);
       run_cycle(h, s, nullptr);
-      hipLaunchKernelGGL(k_from_low<float>, dim3(grid_elems(N, 256)), dim3(256), 0, s,
-                         (const float *)h->U32.p, z, (const uint64_t *)h->act.p, N);
+      hipLaunchKernelGGL(k_to_canonical<float>, dim3(G), dim3(kBlock), 0, s, P,
+                         (const float *)h->U32.p, z);
     } else {
-      hipLaunchKernelGGL(k_to_low<double>, dim3(grid_elems(N, 256)), dim3(256), 0, s, r,
-                         h->B64.p, N);
+      hipLaunchKernelGGL(k_from_canonical<double>, dim3(G), dim3(kBlock), 0, s, P, r, h->B64.p);
       run_cycle(h, s, nullptr);
-      hipLaunchKernelGGL(k_from_low<double>, dim3(grid_elems(N, 256)), dim3(256), 0, s,
-                         (const double *)h->U64.p, z, (const uint64_t *)h->act.p, N);
+      hipLaunchKernelGGL(k_to_canonical<double>, dim3(G), dim3(kBlock), 0, s, P,
+                         (const double *)h->U64.p, z);
     }
     HIP_CHECK(hipGetLastError());
     HIP_CHECK(hipStreamSynchronize(s));
   } catch (const HipError &e) {
-    return fail(MFMG_ERR_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    return hip_fail(e);
   }
   return MFMG_OK;
 }
 
+// --------------------------------------------------------------------------
+// PCG (Algorithm 1)
+// --------------------------------------------------------------------------
+// Launch helpers of one Krylov iteration (Algorithm 1).
 template <class V>
-static void pcg_iterate(mfmg_hierarchy *h, const double *rhs, double *x, double *r, V *r_low,
-                        V *z, const mfmg_solve_params *sp, hipStream_t s) {
-  const Topology &T = h->co->tree->topo;
-  PcgArgs P = pcg_args(h);
-  unsigned G = grid_reduce(T.n_leaf_bricks);
-  const int *done = &h->S.p->done;
-  hipLaunchKernelGGL(k_pcg_init<V>, dim3(G), dim3(kBlock), 0, s, P, rhs, r, r_low, x,
-                     sp->rtol);
-  run_cycle(h, s, done);
-  hipLaunchKernelGGL(k_pcg_rz<V>, dim3(G), dim3(kBlock), 0, s, P, (const double *)r,
-                     (const V *)z, 1);
-  hipLaunchKernelGGL(k_pcg_p<V>, dim3(G), dim3(kBlock), 0, s, P, (const V *)z, h->pd.p, 1);
-  for (int it = 0; it < sp->max_iter; ++it) {
-    hipLaunchKernelGGL(k_pcg_Ap, dim3(G), dim3(kBlock), 0, s, P, (const double *)h->pd.p,
-                       h->Ap.p);
+struct Krylov {
+  mfmg_hierarchy *h;
+  PcgArgs P;
+  hipStream_t s;
+  unsigned G;   // grid of the flat vector kernels
+  unsigned GB;  // one wave per leaf brick
+  int64_t n2;   // leaf entries / 2
+
+  Krylov(mfmg_hierarchy *h_, hipStream_t s_) : h(h_), s(s_) {
+    P = pcg_args(h);
+    G = grid_reduce(h->co->dt->nlb);
+    GB = grid_for(h->co->dt->nlb);
+    n2 = int64_t(h->co->dt->nlb) * 32;
+  }
+  void rz(const double *r, const V *z, int first) const {
+    hipLaunchKernelGGL(k_pcg_rz<V>, dim3(G), dim3(kBlock), 0, s, P, r, z, first, n2);
+  }
+  void pupdate(const V *z, int first) const {
+    hipLaunchKernelGGL(k_pcg_p<V>, dim3(G), dim3(kBlock), 0, s, P, z, h->pd.p, first, n2);
+    const DeviceTopology &D = *h->co->dt;
+    if (D.n_tbricks)
+      hipLaunchKernelGGL(k_average_up, dim3(grid_for(D.n_tbricks)), dim3(kBlock), 0, s, P,
+                         (const int32_t *)D.tbricks.p, D.n_tbricks, h->pd.p);
+  }
+  void Ap(bool trans) const {
+    if (trans)
+      hipLaunchKernelGGL(k_pcg_Ap<true>, dim3(GB), dim3(kBlock), 0, s, P,
+                         (const double *)h->pd.p, h->Ap.p);
+    else
+      hipLaunchKernelGGL(k_pcg_Ap<false>, dim3(GB), dim3(kBlock), 0, s, P,
+                         (const double *)h->pd.p, h->Ap.p);
+    hipLaunchKernelGGL(k_finish_alpha, dim3(1), dim3(1024), 0, s, P, int64_t(GB));
+  }
+  void update(double *x, double *r, V *r_low, int defer) const {
     hipLaunchKernelGGL(k_pcg_update<V>, dim3(G), dim3(kBlock), 0, s, P, x, r, r_low,
-                       (const double *)h->pd.p, (const double *)h->Ap.p);
+                       (const double *)h->pd.p, (const double *)h->Ap.p, defer, n2);
+  }
+};
+
+template <class V>
+static void pcg_iterate(mfmg_hierarchy *h, const double *rhs, double *r, V *r_low, V *z,
+                        const mfmg_solve_params *sp, bool null_space, hipStream_t s) {
+  PcgArgs P = pcg_args(h);
+  unsigned G = grid_reduce(h->co->dt->nlb);
+  const int *done = &h->S.p->done;
+  double na = std::max(1.0, h->n_active);
+  double *x = h->x.p;
+  hipLaunchKernelGGL(k_pcg_init<V>, dim3(G), dim3(kBlock), 0, s, P, rhs, r, r_low, x, sp->rtol);
+  if (null_space) {
+    hipLaunchKernelGGL(k_sum_active, dim3(G), dim3(kBlock), 0, s, P, (const double *)r);
+    hipLaunchKernelGGL(k_shift_mean<V>, dim3(G), dim3(kBlock), 0, s, P, r, r_low, na, 0,
+                       sp->rtol);
+  }
+  Krylov<V> K(h, s);
+  run_cycle(h, s, done);
+  K.rz(r, z, 1);
+  K.pupdate(z, 1);
+  for (int it = 0; it < sp->max_iter; ++it) {
+    K.Ap(false);
+    K.update(x, r, r_low, int(null_space));
+    if (null_space) {
+      hipLaunchKernelGGL(k_sum_active, dim3(G), dim3(kBlock), 0, s, P, (const double *)r);
+      hipLaunchKernelGGL(k_shift_mean<V>, dim3(G), dim3(kBlock), 0, s, P, r, r_low, na, 1,
+                         sp->rtol);
+    }
     run_cycle(h, s, done);
-    hipLaunchKernelGGL(k_pcg_rz<V>, dim3(G), dim3(kBlock), 0, s, P, (const double *)r,
-                       (const V *)z, 0);
-    hipLaunchKernelGGL(k_pcg_p<V>, dim3(G), dim3(kBlock), 0, s, P, (const V *)z, h->pd.p, 0);
+    K.rz(r, z, 0);
+    K.pupdate(z, 0);
     HIP_CHECK(hipMemcpyAsync(h->hostS, h->S.p, sizeof(Scalars), hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
     if (h->hostS->done) break;
   }
-  hipLaunchKernelGGL(k_full, dim3(grid_for(T.n_leaf_bricks)), dim3(kBlock), 0, s, P,
-                     (const double *)x, h->Xf.p);
-  hipLaunchKernelGGL(k_true_resid, dim3(G), dim3(kBlock), 0, s, P, rhs, (const double *)h->Xf.p);
+  if (null_space) {
+    // zero-mean solution, then the true residual shifted to zero mean
+    hipLaunchKernelGGL(k_sum_active, dim3(G), dim3(kBlock), 0, s, P, (const double *)x);
+    hipLaunchKernelGGL(k_shift_mean<double>, dim3(G), dim3(kBlock), 0, s, P, x,
+                       (double *)nullptr, na, 3, 0.0);
+  }
+  hipLaunchKernelGGL(k_full, dim3(G), dim3(kBlock), 0, s, P, (const double *)x, h->Xf.p, 0);
+  if (null_space) {
+    hipLaunchKernelGGL(k_residual_vec, dim3(G), dim3(kBlock), 0, s, P, rhs,
+                       (const double *)h->Xf.p, h->Ap.p);
+    hipLaunchKernelGGL(k_sum_active, dim3(G), dim3(kBlock), 0, s, P, (const double *)h->Ap.p);
+    hipLaunchKernelGGL(k_shift_mean<double>, dim3(G), dim3(kBlock), 0, s, P, h->Ap.p,
+                       (double *)nullptr, na, 2, 0.0);
+  } else {
+    hipLaunchKernelGGL(k_true_resid, dim3(G), dim3(kBlock), 0, s, P, rhs,
+                       (const double *)h->Xf.p);
+  }
   HIP_CHECK(hipGetLastError());
 }
 
@@ -873,8 +912,9 @@ extern "C" mfmg_status mfmg_pcg_solve(mfmg_hierarchy *h, const double *rhs, doub
                                       mfmg_solve_stats *stats, double *hist) {
   if (!h || !rhs || !p || !sp) return fail(MFMG_ERR_INVALID_ARG, "NULL argument");
   if (!(sp->rtol >= 0.0) || sp->max_iter < 0) return fail(MFMG_ERR_INVALID_ARG, "bad params");
-  if (sp->null_space == 1 || (sp->null_space == -1 && !h->co->has_dirichlet))
-    return fail(MFMG_ERR_INVALID_ARG, "null-space projection not available in this build");
+  if (sp->null_space < -1 || sp->null_space > 1)
+    return fail(MFMG_ERR_INVALID_ARG, "null_space must be -1, 0 or 1");
+  bool ns = sp->null_space == 1 || (sp->null_space == -1 && !h->co->has_dirichlet);
   hipStream_t s = (hipStream_t)stream;
   mfmg_status st = MFMG_OK;
   try {
@@ -884,9 +924,12 @@ extern "C" mfmg_status mfmg_pcg_solve(mfmg_hierarchy *h, const double *rhs, doub
     HIP_CHECK(hipEventCreate(&e1));
     HIP_CHECK(hipEventRecord(e0, s));
     if (h->prm.precision == MFMG_MIXED)
-      pcg_iterate<float>(h, rhs, p, h->r.p, h->B32.p, h->U32.p, sp, s);
+      pcg_iterate<float>(h, rhs, h->r.p, h->B32.p, h->U32.p, sp, ns, s);
     else
-      pcg_iterate<double>(h, rhs, p, h->B64.p, (double *)nullptr, h->U64.p, sp, s);
+      pcg_iterate<double>(h, rhs, h->B64.p, (double *)nullptr, h->U64.p, sp, ns, s);
+    PcgArgs P = pcg_args(h);
+    hipLaunchKernelGGL(k_to_canonical<double>, dim3(grid_for(h->co->dt->nlb)), dim3(kBlock), 0,
+                       s, P, (const double *)h->x.p, p);
     HIP_CHECK(hipEventRecord(e1, s));
     HIP_CHECK(hipMemcpyAsync(h->hostS, h->S.p, sizeof(Scalars), hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
@@ -910,11 +953,62 @@ extern "C" mfmg_status mfmg_pcg_solve(mfmg_hierarchy *h, const double *rhs, doub
       HIP_CHECK(hipMemcpy(hist, h->hist.p, (size_t(sp->max_iter) + 1) * sizeof(double),
                           hipMemcpyDeviceToHost));
   } catch (const HipError &e) {
-    return fail(MFMG_ERR_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    return hip_fail(e);
   }
   if (st == MFMG_ERR_BREAKDOWN) return fail(st, "PCG breakdown: (r,z) or (p,Ap) not positive");
   if (st == MFMG_NOT_CONVERGED) g_err = "not converged within max_iter";
   return st;
+}
+
+// Adjoint PCG: A^T lambda = g preconditioned by M^T (Algorithm 1 with the
+// transposed operator and cycle).
+template <class V>
+static void pcg_adjoint_iterate(mfmg_hierarchy *h, const double *g, V *z,
+                                const mfmg_solve_params *sp, bool null_space, hipStream_t s) {
+  PcgArgs P = pcg_args(h);
+  unsigned G = grid_reduce(h->co->dt->nlb);
+  double na = std::max(1.0, h->n_active);
+  double *x = h->x.p, *r = h->rA.p;
+  hipLaunchKernelGGL(k_pcg_init<V>, dim3(G), dim3(kBlock), 0, s, P, g, r, (V *)nullptr, x,
+                     sp->rtol);
+  if (null_space) {
+    hipLaunchKernelGGL(k_sum_active, dim3(G), dim3(kBlock), 0, s, P, (const double *)r);
+    hipLaunchKernelGGL(k_shift_mean<V>, dim3(G), dim3(kBlock), 0, s, P, r, (V *)nullptr, na, 0,
+                       sp->rtol);
+  }
+  HIP_CHECK(hipMemcpyAsync(h->hostS, h->S.p, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  if (!h->hostS->done) {
+    Krylov<V> K(h, s);
+    run_cycle_T(h, r, s);
+    K.rz(r, z, 1);
+    K.pupdate(z, 1);
+    for (int it = 0; it < sp->max_iter; ++it) {
+      K.Ap(true);
+      K.update(x, r, (V *)nullptr, int(null_space));
+      if (null_space) {
+        hipLaunchKernelGGL(k_sum_active, dim3(G), dim3(kBlock), 0, s, P, (const double *)r);
+        hipLaunchKernelGGL(k_shift_mean<V>, dim3(G), dim3(kBlock), 0, s, P, r, (V *)nullptr, na,
+                           1, sp->rtol);
+      }
+      HIP_CHECK(hipMemcpyAsync(h->hostS, h->S.p, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+      HIP_CHECK(hipStreamSynchronize(s));
+      if (h->hostS->done) break;
+      run_cycle_T(h, r, s);
+      K.rz(r, z, 0);
+      K.pupdate(z, 0);
+    }
+  }
+  if (null_space) {
+    hipLaunchKernelGGL(k_sum_active, dim3(G), dim3(kBlock), 0, s, P, (const double *)x);
+    hipLaunchKernelGGL(k_shift_mean<double>, dim3(G), dim3(kBlock), 0, s, P, x,
+                       (double *)nullptr, na, 3, 0.0);
+  }
+  // true residual ||g - A^T lambda||
+  hipLaunchKernelGGL(k_full, dim3(G), dim3(kBlock), 0, s, P, (const double *)x, h->Xf.p, 0);
+  hipLaunchKernelGGL(k_apply<true>, dim3(G), dim3(kBlock), 0, s, P, (const double *)h->Xf.p,
+                     h->Ap.p);
+  HIP_CHECK(hipGetLastError());
 }
 
 extern "C" mfmg_status mfmg_pcg_solve_adjoint(mfmg_hierarchy *h, const double *p,
@@ -922,9 +1016,128 @@ extern "C" mfmg_status mfmg_pcg_solve_adjoint(mfmg_hierarchy *h, const double *p
                                               double *dL_dbeta,
                                               const mfmg_solve_params *sp, void *stream,
                                               mfmg_solve_stats *stats) {
-  (void)h; (void)p; (void)dL_dp; (void)lambda; (void)dL_dbeta; (void)sp; (void)stream;
-  (void)stats;
-  return fail(MFMG_ERR_INVALID_ARG, "adjoint solve not available in this build");
+  if (!h || !p || !dL_dp || !lambda || !dL_dbeta || !sp)
+    return fail(MFMG_ERR_INVALID_ARG, "NULL argument");
+  if (!(sp->rtol >= 0.0) || sp->max_iter < 0) return fail(MFMG_ERR_INVALID_ARG, "bad params");
+  if (sp->null_space < -1 || sp->null_space > 1)
+    return fail(MFMG_ERR_INVALID_ARG, "null_space must be -1, 0 or 1");
+  bool ns = sp->null_space == 1 || (sp->null_space == -1 && !h->co->has_dirichlet);
+  hipStream_t s = (hipStream_t)stream;
+  const Topology &T = h->co->tree->topo;
+  const DeviceTopology &D = *h->co->dt;
+  mfmg_status st = MFMG_OK;
+  try {
+    h->hist.alloc(size_t(sp->max_iter) + 2);
+    if (!h->rA.p) h->rA.alloc(size_t(D.nlb) * 64);
+    if (!h->f_owner.p) {
+      // canonical face list and per-brick tables for the gradient
+      int64_t nf = T.n_faces;
+      std::vector<int64_t> owner(nf), other(nf);
+      std::vector<int8_t> dir(nf), kind(nf), lvl(T.n_leaf_bricks);
+      for (int64_t b = 0; b < T.n_leaf_bricks; ++b) {
+        lvl[b] = T.level[b];
+        for (int m = 0; m < kCells; ++m) {
+          int64_t c = b * kCells + m;
+          int64_t f = T.cell_fbase[c];
+          for (int d = 0; d < 6; ++d) {
+            if (!((T.cell_fmask[c] >> d) & 1)) continue;
+            int64_t o;
+            int k = T.cell_neighbour(b, m, d, &o);
+            owner[f] = c;
+            dir[f] = int8_t(d);
+            other[f] = o;
+            kind[f] = int8_t(k);
+            ++f;
+          }
+        }
+      }
+      h->f_owner.upload(owner, s);
+      h->f_other.upload(other, s);
+      h->f_dir.upload(dir, s);
+      h->f_kind.upload(kind, s);
+      h->leaf_level.upload(lvl, s);
+      h->canon_act.alloc(size_t(D.nlb));
+      hipLaunchKernelGGL(k_canonical_act, dim3(grid_elems(D.nlb, 256)), dim3(256), 0, s,
+                         (const BrickMeta *)h->meta.p, (const int32_t *)D.canon.p, D.nlb,
+                         h->canon_act.p);
+      HIP_CHECK(hipStreamSynchronize(s));
+    }
+    hipEvent_t e0, e1;
+    HIP_CHECK(hipEventCreate(&e0));
+    HIP_CHECK(hipEventCreate(&e1));
+    HIP_CHECK(hipEventRecord(e0, s));
+    if (h->prm.precision == MFMG_MIXED) {
+      alloc_transpose(h, h->T32);
+      pcg_adjoint_iterate<float>(h, dL_dp, h->T32[1].p, sp, ns, s);
+    } else {
+      alloc_transpose(h, h->T64);
+      pcg_adjoint_iterate<double>(h, dL_dp, h->T64[1].p, sp, ns, s);
+    }
+    PcgArgs P = pcg_args(h);
+    unsigned G = grid_for(D.nlb);
+    hipLaunchKernelGGL(k_to_canonical<double>, dim3(G), dim3(kBlock), 0, s, P,
+                       (const double *)h->x.p, lambda);
+    // true residual of the adjoint system: canonical A^T lambda vs dL/dp
+    hipLaunchKernelGGL(k_to_canonical<double>, dim3(G), dim3(kBlock), 0, s, P,
+                       (const double *)h->Ap.p, h->Xf.p);
+    GradArgs A;
+    A.owner = h->f_owner.p;
+    A.other = h->f_other.p;
+    A.dir = h->f_dir.p;
+    A.kind = h->f_kind.p;
+    A.level = h->leaf_level.p;
+    A.act = h->canon_act.p;
+    A.lam = lambda;
+    A.p = p;
+    for (int d = 0; d < 6; ++d) A.bc[d] = h->co->bc.bc[d];
+    A.theta = h->co->bc.theta;
+    A.n_faces = T.n_faces;
+    A.g = dL_dbeta;
+    hipLaunchKernelGGL(k_face_gradient, dim3(grid_elems(T.n_faces, 256)), dim3(256), 0, s, A);
+    HIP_CHECK(hipEventRecord(e1, s));
+    HIP_CHECK(hipMemcpyAsync(h->hostS, h->S.p, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    float ms = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    // ||dL/dp - A^T lambda|| on the host from the canonical vectors
+    int64_t N = int64_t(D.nlb) * 64;
+    std::vector<double> gt(N), at(N);
+    std::vector<uint64_t> am(D.nlb);
+    HIP_CHECK(hipMemcpy(gt.data(), dL_dp, N * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_CHECK(hipMemcpy(at.data(), h->Xf.p, N * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_CHECK(hipMemcpy(am.data(), h->canon_act.p, D.nlb * sizeof(uint64_t),
+                        hipMemcpyDeviceToHost));
+    double tr = 0.0, sum = 0.0, na = 0.0;
+    for (int64_t i = 0; i < N; ++i)
+      if ((am[i >> 6] >> (i & 63)) & 1ull) {
+        double t = gt[i] - at[i];
+        tr += t * t;
+        sum += t;
+        na += 1.0;
+      }
+    if (ns && na > 0) tr -= sum * sum / na;
+    const Scalars &S = *h->hostS;
+    if (S.status == -5)
+      st = MFMG_ERR_BREAKDOWN;
+    else if (S.rr0 > 0.0 && !(S.rr <= S.tol2))
+      st = MFMG_NOT_CONVERGED;
+    if (stats) {
+      stats->iters = S.iters;
+      stats->status = st;
+      stats->rel_resid_recur = S.rr0 > 0.0 ? std::sqrt(S.rr / S.rr0) : 0.0;
+      stats->rel_resid_true = S.rr0 > 0.0 ? std::sqrt(std::max(tr, 0.0) / S.rr0) : 0.0;
+      stats->seconds = ms * 1e-3;
+    }
+  } catch (const HipError &e) {
+    return hip_fail(e);
+  } catch (const std::bad_alloc &) {
+    return fail(MFMG_ERR_OOM, "host allocation failed");
+  }
+  if (st == MFMG_ERR_BREAKDOWN) return fail(st, "PCG breakdown: (r,z) or (p,Ap) not positive");
+  if (st == MFMG_NOT_CONVERGED) g_err = "not converged within max_iter";
+  return st;
 }
 
 // --------------------------------------------------------------------------
@@ -938,8 +1151,7 @@ double smooth_bytes(const mfmg_hierarchy *h, int l) {
   bool mixed = h->prm.precision == MFMG_MIXED;
   double V = mixed ? 4.0 : 8.0;
   double CL = mixed ? 4.0 : 8.0, CI = mixed ? 2.0 : 8.0;
-  double n_in = double(D.in_n[l]) * 64, n_all = double(D.all_n[l]) * 64;
-  double n_leaf = n_all - n_in;
+  double n_in = double(D.range[l].n_inner) * 64, n_leaf = double(D.range[l].n_leaf) * 64;
   auto per = [&](double C) { return V + 0.5 * V + 0.5 * C + 3.0 * C + 0.5 * V; };
   return n_leaf * per(CL) + n_in * per(CI);
 }
@@ -951,12 +1163,12 @@ double cycle_bytes(const mfmg_hierarchy *h) {
   bool mixed = p.precision == MFMG_MIXED;
   double V = mixed ? 4.0 : 8.0;
   double CL = mixed ? 4.0 : 8.0, CI = mixed ? 2.0 : 8.0;
-  double total = double(h->co->tree->topo.n_leaves()) * V;  // zero the leaf iterate
+  double total = double(h->co->dt->nlb) * 64 * V;  // zero the leaf iterate
   // visits of each level per cycle: mu^(L - l)
   for (int l = h->L; l >= h->lc; --l) {
     double visits = std::pow(double(p.mu), double(h->L - l));
-    double n_in = double(D.in_n[l]) * 64, n_all = double(D.all_n[l]) * 64;
-    double n_leaf = n_all - n_in;
+    double n_in = double(D.range[l].n_inner) * 64, n_leaf = double(D.range[l].n_leaf) * 64;
+    double n_all = n_in + n_leaf;
     double cells_coef = n_leaf * 4.0 * CL + n_in * 4.0 * CI;  // 4 coefficients
     if (l == h->lc) {
       total += visits * 2.0 * p.nu_coarse * smooth_bytes(h, l);
@@ -964,7 +1176,7 @@ double cycle_bytes(const mfmg_hierarchy *h) {
     }
     double lvl = 2.0 * (p.nu_pre + p.nu_post) * smooth_bytes(h, l);
     lvl += n_all * (2.0 * V + 3.0 * V / 8.0) + cells_coef;  // residual + restriction
-    double c_in = double(D.in_n[l - 1]) * 64;                 // FAS right-hand side
+    double c_in = double(D.range[l - 1].n_inner) * 64;        // FAS right-hand side
     double c_coef = c_in * 4.0 * CI;
     lvl += c_in * 3.0 * V + c_coef;
     lvl += n_all * (2.0 * V + 2.0 * V / 8.0);                 // prolongation
@@ -980,7 +1192,6 @@ extern "C" mfmg_status mfmg_profile(mfmg_hierarchy *h, int what, int level, int 
                                     double *bytes_per_launch) {
   if (!h || !ms_per_launch || reps < 1) return fail(MFMG_ERR_INVALID_ARG, "bad argument");
   hipStream_t s = (hipStream_t)stream;
-  const Topology &T = h->co->tree->topo;
   if (what == MFMG_PROFILE_SMOOTH && (level < h->lc || level > h->L))
     return fail(MFMG_ERR_INVALID_ARG, "level out of range");
   try {
@@ -994,15 +1205,15 @@ extern "C" mfmg_status mfmg_profile(mfmg_hierarchy *h, int what, int level, int 
           Cycle<float, float, __half> c{h, h->coef32.p, h->coef16.p, h->tc32.p,
                                         h->U32.p, h->B32.p, h->S32.p, nullptr, s};
           auto A = c.args(level, false);
-          hipLaunchKernelGGL((k_smooth<float, float, __half>), dim3(grid_for(A.n)),
+          hipLaunchKernelGGL((k_smooth<float, float, __half>), dim3(grid_for(A.R.n())),
                              dim3(kBlock), 0, s, A, 0);
         } else {
           Cycle<double, double, double> c{h, h->coef64.p,
-                                          h->coef64.p + T.n_leaf_bricks * 256,
+                                          h->coef64.p + int64_t(h->co->dt->nlb) * 256,
                                           h->co->tc.p, h->U64.p, h->B64.p, h->S64.p,
                                           nullptr, s};
           auto A = c.args(level, false);
-          hipLaunchKernelGGL((k_smooth<double, double, double>), dim3(grid_for(A.n)),
+          hipLaunchKernelGGL((k_smooth<double, double, double>), dim3(grid_for(A.R.n())),
                              dim3(kBlock), 0, s, A, 0);
         }
       } else {

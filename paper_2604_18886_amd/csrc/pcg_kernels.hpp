@@ -1,0 +1,561 @@
+// HIP kernels of the outer Krylov solver (Algorithm 1, FP64): the composite
+// leaf operator with its T-junction rows (Section 3.1) and its transpose,
+// the PCG vector updates with fused deterministic dot products, and the
+// gather/scatter between the canonical leaf order of the C ABI and the
+// level-major device order.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace mfmg {
+
+struct PcgArgs {
+  Topo T;
+  const double *C;       // FP64 coefficients of all bricks (device order)
+  const double *TC;      // FP64 plus-side T-face coefficients
+  const int32_t *canon;  // device leaf brick -> canonical leaf brick
+  Scalars *S;
+  double *partials;
+  double *hist;
+};
+
+__device__ __forceinline__ void leaf_cell(const PcgArgs &P, uint32_t b, int m, double &c,
+                                          double &k0, double &k1, double &k2) {
+  const double *cf = P.C + b * 256u;
+  c = cf[m];
+  k0 = cf[64 + m];
+  k1 = cf[128 + m];
+  k2 = cf[192 + m];
+}
+
+// Composite leaf operator, forward.  X and C cover all bricks: where a
+// leaf's same-level neighbour is an inner cell P, X holds the mean of P's
+// active children (written by average_up) and C holds P's Algorithm 3
+// coefficients, whose face coefficient is the sum of the fine sub-face
+// coefficients over 2 -- the coarse side of the T-junction.  The fine side
+// uses the ghost of Eq. (10).
+__device__ __forceinline__ double composite_Au(const Topo &T, const double *__restrict__ C,
+                                               const double *__restrict__ TC,
+                                               const double *__restrict__ X,
+                                               const BrickMeta &M, int m, double u, double c,
+                                               double k0, double k1, double k2) {
+  double v[6], k[6];
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    int a = d >> 1;
+    int p = dev_partner(m, d);
+    double kown = a == 0 ? k0 : (a == 1 ? k1 : k2);
+    v[d] = shfl(u, p);
+    k[d] = (d & 1) ? shfl(kown, p) : kown;
+  }
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    int p = dev_partner(m, d);
+    if (dev_outside(m, d) && M.nbr[d] >= 0) {
+      v[d] = X[uint32_t(M.nbr[d]) * 64u + p];
+      if (d & 1) k[d] = C[uint32_t(M.nbr[d]) * 256u + (1 + (d >> 1)) * 64 + p];
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < 6; ++d)
+    if (dev_outside(m, d) && ((M.flags >> (16 + d)) & 1u)) v[d] = 0.0;
+  uint64_t amask = act_mask(M);
+  bool act = (amask >> m) & 1ull;
+  if (M.flags & kFlagT) {
+    double s = group8_sum(act ? u : 0.0);
+    int cnt = __popcll((amask >> (m & 56)) & 0xffull);
+    double ubar = cnt ? s / double(cnt) : 0.0;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      if (((M.flags >> d) & 1u) && dev_outside(m, d)) {
+        int32_t J = dev_decode_coarse(M.nbr[d]);
+        const BrickMeta MJ = T.meta[J];
+        double uJ = X[uint32_t(J) * 64u + coarse_local(M, m, d, MJ)];
+        v[d] = u + (uJ - ubar) * 0.5;
+        if (d & 1)
+          k[d] = TC[uint32_t(M.tplus) * 48u + (d >> 1) * 16 + dev_face_index(m, d >> 1)];
+      }
+    }
+  }
+  double acc = c * u;
+#pragma unroll
+  for (int d = 0; d < 6; ++d) acc -= k[d] * v[d];
+  return act ? acc : 0.0;
+}
+
+// Transposed composite operator (adjoint path).  Its T-junction blocks are
+// the transposes of the rank-one blocks of A: a fine cell's row gets, for
+// every active sibling, (1/n) sum over the sibling group's T-faces of
+// (k/2)(x_i - x_J); a coarse leaf's row gets - sum_f (k_f/2) x_f over the
+// fine face cells f in place of K_F times their parent's mean.  X is a
+// leaf-sized vector in device order; inner neighbours are read through
+// their children.
+__device__ __forceinline__ double composite_AuT(const Topo &T, const double *__restrict__ C,
+                                                const double *__restrict__ TC,
+                                                const double *__restrict__ X,
+                                                const BrickMeta &M, int m, double u, double c,
+                                                double k0, double k1, double k2) {
+  uint64_t amask = act_mask(M);
+  bool act = (amask >> m) & 1ull;
+  int cnt = __popcll((amask >> (m & 56)) & 0xffull);
+  double acc = c * u;
+  double tpart = 0.0;  // this cell's sum of (k/2)(x_m - x_J) over its T-faces
+  for (int d = 0; d < 6; ++d) {
+    int a = d >> 1;
+    int p = dev_partner(m, d);
+    double kown = a == 0 ? k0 : (a == 1 ? k1 : k2);
+    double v = shfl(u, p);
+    double kp = shfl(kown, p);
+    double k = (d & 1) ? kp : kown;
+    if (dev_outside(m, d)) {
+      int32_t nb = M.nbr[d];
+      if (nb >= 0 && uint32_t(nb) < T.nlb) {
+        v = X[uint32_t(nb) * 64u + p];
+        if (d & 1) k = C[uint32_t(nb) * 256u + (1 + a) * 64 + p];
+      } else if (nb >= 0) {
+        int32_t cb = T.child[8 * int64_t(nb) + (p >> 3)];
+        int32_t slot = T.meta[cb].tplus;
+        int base = (p & 7) << 3;
+        int facebit = (d & 1) ? 0 : 1;  // children on P's face toward this cell
+        double sumkv = 0.0;
+        for (int t = 0; t < 8; ++t) {
+          if (((t >> a) & 1) != facebit) continue;
+          int q = base | t;
+          double kc = (d & 1) ? C[uint32_t(cb) * 256u + (1 + a) * 64 + q]
+                              : TC[uint32_t(slot) * 48u + a * 16 + dev_face_index(q, a)];
+          sumkv += kc * 0.5 * X[uint32_t(cb) * 64u + q];
+        }
+        acc -= sumkv;
+        continue;
+      } else if (nb == dWall) {
+        v = 0.0;
+      } else {
+        int32_t J = dev_decode_coarse(nb);
+        const BrickMeta MJ = T.meta[J];
+        double uJ = X[uint32_t(J) * 64u + coarse_local(M, m, d, MJ)];
+        if (d & 1) k = TC[uint32_t(M.tplus) * 48u + a * 16 + dev_face_index(m, a)];
+        acc -= k * u;
+        tpart += k * 0.5 * (u - uJ);
+        continue;
+      }
+    }
+    acc -= k * v;
+  }
+  double S = group8_sum(tpart);
+  if (act && cnt) acc += S / double(cnt);
+  return act ? acc : 0.0;
+}
+
+// Mean of the active cells of each aligned sibling group of a leaf brick
+// with a T-face, written to the parent cells' slots of a full-size vector:
+// the value the forward composite operator reads for an inner neighbour.
+__device__ __forceinline__ void average_up(double *__restrict__ X, const BrickMeta &M, int m,
+                                           double x) {
+  uint64_t amask = act_mask(M);
+  bool act = (amask >> m) & 1ull;
+  double s = group8_sum(act ? x : 0.0);
+  int cnt = __popcll((amask >> (m & 56)) & 0xffull);
+  if ((m & 7) == 0)
+    X[uint32_t(M.parent) * 64u + ((octant_of(M) << 3) | (m >> 3))] = cnt ? s / double(cnt) : 0.0;
+}
+
+// grid-stride loop of one wave over the leaf bricks
+#define LEAF_LOOP(P)                                                     \
+  int m = threadIdx.x & (kWave - 1);                                     \
+  for (uint32_t b = blockIdx.x * kWavesPerBlock + wave_id(); b < (P).T.nlb; \
+       b += gridDim.x * kWavesPerBlock)
+
+// r = rhs (canonical order) on active cells, x = 0, ||r||^2
+template <class V>
+__global__ void __launch_bounds__(kBlock) k_pcg_init(PcgArgs P, const double *rhs, double *r,
+                                                     V *r_low, double *x, double rtol) {
+  double part = 0.0;
+  LEAF_LOOP(P) {
+    const BrickMeta M = P.T.meta[b];
+    bool act = (act_mask(M) >> m) & 1ull;
+    double v = act ? rhs[uint32_t(P.canon[b]) * 64u + m] : 0.0;
+    r[b * 64u + m] = v;
+    if (r_low) r_low[b * 64u + m] = V(v);
+    x[b * 64u + m] = 0.0;
+    part += v * v;
+  }
+  Scalars *S = P.S;
+  block_reduce_finish(part, P.partials, &S->ticket[0], [&](double tot) {
+    S->rr0 = tot;
+    S->rr = tot;
+    S->tol2 = rtol * rtol * tot;
+    S->iters = 0;
+    S->status = 0;
+    S->done = (tot == 0.0) || !(tot < INFINITY);
+    if (!(tot < INFINITY)) S->status = -5;
+    S->rz = 0.0;
+    P.hist[0] = tot > 0.0 ? 1.0 : 0.0;
+  });
+}
+
+// Flat vector kernels: the leaf vectors of the Krylov iteration are
+// contiguous (device order) and zero on inactive cells, so x/r updates,
+// (r, z) and p = z + beta p are plain streams of 2-element vectors.
+template <class V>
+struct Vec2;
+template <>
+struct Vec2<double> {
+  using T = double2;
+};
+template <>
+struct Vec2<float> {
+  using T = float2;
+};
+
+// (r, z) and beta = (r, z) / (r, z)_old (beta = 0 on the first call)
+template <class V>
+__global__ void __launch_bounds__(kBlock) k_pcg_rz(PcgArgs P, const double *r, const V *z,
+                                                   int first, int64_t n2) {
+  if (P.S->done) return;
+  double part = 0.0;
+  const double2 *r2 = reinterpret_cast<const double2 *>(r);
+  const typename Vec2<V>::T *z2 = reinterpret_cast<const typename Vec2<V>::T *>(z);
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n2;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    double2 a = r2[i];
+    auto b = z2[i];
+    part += a.x * double(b.x) + a.y * double(b.y);
+  }
+  Scalars *S = P.S;
+  block_reduce_finish(part, P.partials, &S->ticket[1], [&](double tot) {
+    if (!(tot > 0.0) || !(tot < INFINITY)) {
+      S->status = -5;
+      S->done = 1;
+      return;
+    }
+    S->beta = first ? 0.0 : tot / S->rz;
+    S->rz = tot;
+  });
+}
+
+// p = z + beta p (p = z on the first call)
+template <class V>
+__global__ void __launch_bounds__(kBlock) k_pcg_p(PcgArgs P, const V *z, double *p, int first,
+                                                  int64_t n2) {
+  if (P.S->done) return;
+  double beta = first ? 0.0 : P.S->beta;
+  double2 *p2 = reinterpret_cast<double2 *>(p);
+  const typename Vec2<V>::T *z2 = reinterpret_cast<const typename Vec2<V>::T *>(z);
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n2;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    auto b = z2[i];
+    double2 v;
+    if (first) {
+      v.x = double(b.x);
+      v.y = double(b.y);
+    } else {
+      double2 a = p2[i];
+      v.x = double(b.x) + beta * a.x;
+      v.y = double(b.y) + beta * a.y;
+    }
+    p2[i] = v;
+  }
+}
+
+// Parent means of the leaf bricks with T-faces (list), read by the forward
+// composite operator for inner neighbours.
+__global__ void __launch_bounds__(kBlock) k_average_up(PcgArgs P, const int32_t *list,
+                                                       uint32_t n, double *X) {
+  if (P.S && P.S->done) return;
+  uint32_t i = blockIdx.x * kWavesPerBlock + wave_id();
+  int m = threadIdx.x & (kWave - 1);
+  if (i >= n) return;
+  uint32_t b = uint32_t(list[i]);
+  const BrickMeta M = P.T.meta[b];
+  average_up(X, M, m, X[b * 64u + m]);
+}
+
+// Ap = A p (TRANS: A^T p, for the adjoint), one wave per leaf brick; each
+// workgroup stores its partial (p, Ap), k_finish_alpha adds them.
+template <bool TRANS>
+__global__ void __launch_bounds__(kBlock) k_pcg_Ap(PcgArgs P, const double *p, double *Ap) {
+  if (P.S->done) return;
+  uint32_t b = blockIdx.x * kWavesPerBlock + wave_id();
+  int m = threadIdx.x & (kWave - 1);
+  double part = 0.0;
+  if (b < P.T.nlb) {
+    const BrickMeta M = P.T.meta[b];
+    double c, k0, k1, k2;
+    leaf_cell(P, b, m, c, k0, k1, k2);
+    double u = p[b * 64u + m];
+    double y = TRANS ? composite_AuT(P.T, P.C, P.TC, p, M, m, u, c, k0, k1, k2)
+                     : composite_Au(P.T, P.C, P.TC, p, M, m, u, c, k0, k1, k2);
+    Ap[b * 64u + m] = y;
+    part = u * y;
+  }
+  __shared__ double red[kWavesPerBlock];
+  part = wave_sum(part);
+  if (m == 0) red[threadIdx.x >> 6] = part;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kWavesPerBlock; ++w) s += red[w];
+    P.partials[blockIdx.x] = s;
+  }
+}
+
+// (p, Ap) from the per-workgroup partials in fixed order; alpha = (r,z)/(p,Ap)
+__global__ void __launch_bounds__(1024) k_finish_alpha(PcgArgs P, int64_t n) {
+  if (P.S->done) return;
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += P.partials[i];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot = 0.0;
+    for (unsigned w = 0; w < blockDim.x / 64; ++w) tot += red[w];
+    Scalars *S = P.S;
+    S->pAp = tot;
+    if (!(tot > 0.0) || !(tot < INFINITY)) {
+      S->status = -5;
+      S->done = 1;
+    } else {
+      S->alpha = S->rz / tot;
+    }
+  }
+}
+
+// x += alpha p, r -= alpha Ap, ||r||^2 and the stop test
+template <class V>
+__global__ void __launch_bounds__(kBlock) k_pcg_update(PcgArgs P, double *x, double *r,
+                                                       V *r_low, const double *p,
+                                                       const double *Ap, int defer,
+                                                       int64_t n2) {
+  if (P.S->done) return;
+  double alpha = P.S->alpha;
+  double part = 0.0;
+  double2 *x2 = reinterpret_cast<double2 *>(x);
+  double2 *r2 = reinterpret_cast<double2 *>(r);
+  const double2 *p2 = reinterpret_cast<const double2 *>(p);
+  const double2 *a2 = reinterpret_cast<const double2 *>(Ap);
+  typename Vec2<V>::T *l2 = reinterpret_cast<typename Vec2<V>::T *>(r_low);
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n2;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    double2 xv = x2[i], rv = r2[i], pv = p2[i], av = a2[i];
+    xv.x += alpha * pv.x;
+    xv.y += alpha * pv.y;
+    rv.x -= alpha * av.x;
+    rv.y -= alpha * av.y;
+    x2[i] = xv;
+    r2[i] = rv;
+    if (r_low) {
+      typename Vec2<V>::T lv;
+      lv.x = V(rv.x);
+      lv.y = V(rv.y);
+      l2[i] = lv;
+    }
+    part += rv.x * rv.x + rv.y * rv.y;
+  }
+  Scalars *S = P.S;
+  if (defer) return;  // the null-space shift completes this step
+  block_reduce_finish(part, P.partials, &S->ticket[3], [&](double tot) {
+    S->rr = tot;
+    S->iters += 1;
+    P.hist[S->iters] = S->rr0 > 0.0 ? sqrt(tot / S->rr0) : 0.0;
+    if (!(tot < INFINITY)) {
+      S->status = -5;
+      S->done = 1;
+    } else if (tot <= S->tol2) {
+      S->done = 1;
+    }
+  });
+}
+
+// X (full size, device order) from a leaf vector x; canonical = 1 when x is
+// in canonical order.  Inactive cells are zeroed; bricks with T-faces write
+// the sibling-group means into the parent slots.
+__global__ void __launch_bounds__(kBlock) k_full(PcgArgs P, const double *x, double *X,
+                                                 int canonical) {
+  LEAF_LOOP(P) {
+    const BrickMeta M = P.T.meta[b];
+    uint32_t src = (canonical ? uint32_t(P.canon[b]) : b) * 64u + m;
+    double v = ((act_mask(M) >> m) & 1ull) ? x[src] : 0.0;
+    X[b * 64u + m] = v;
+    if (M.flags & kFlagT) average_up(X, M, m, v);
+  }
+}
+
+// y = A X (X from k_full) or y = A^T X, y in device order
+template <bool TRANS>
+__global__ void __launch_bounds__(kBlock) k_apply(PcgArgs P, const double *X, double *y) {
+  LEAF_LOOP(P) {
+    const BrickMeta M = P.T.meta[b];
+    double c, k0, k1, k2;
+    leaf_cell(P, b, m, c, k0, k1, k2);
+    double u = X[b * 64u + m];
+    y[b * 64u + m] = TRANS ? composite_AuT(P.T, P.C, P.TC, X, M, m, u, c, k0, k1, k2)
+                           : composite_Au(P.T, P.C, P.TC, X, M, m, u, c, k0, k1, k2);
+  }
+}
+
+// ||rhs - A X||^2 over active cells, rhs in canonical order
+__global__ void __launch_bounds__(kBlock) k_true_resid(PcgArgs P, const double *rhs,
+                                                       const double *X) {
+  double part = 0.0;
+  LEAF_LOOP(P) {
+    const BrickMeta M = P.T.meta[b];
+    double c, k0, k1, k2;
+    leaf_cell(P, b, m, c, k0, k1, k2);
+    double y = composite_Au(P.T, P.C, P.TC, X, M, m, X[b * 64u + m], c, k0, k1, k2);
+    bool act = (act_mask(M) >> m) & 1ull;
+    double t = act ? rhs[uint32_t(P.canon[b]) * 64u + m] - y : 0.0;
+    part += t * t;
+  }
+  Scalars *S = P.S;
+  block_reduce_finish(part, P.partials, &S->ticket[0], [&](double tot) { S->tr = tot; });
+}
+
+// device-order leaf vector of type V -> canonical FP64 (inactive cells 0)
+template <class V>
+__global__ void __launch_bounds__(kBlock) k_to_canonical(PcgArgs P, const V *src, double *dst) {
+  LEAF_LOOP(P) {
+    const BrickMeta M = P.T.meta[b];
+    double v = ((act_mask(M) >> m) & 1ull) ? double(src[b * 64u + m]) : 0.0;
+    dst[uint32_t(P.canon[b]) * 64u + m] = v;
+  }
+}
+
+// canonical FP64 -> device-order leaf vector of type V
+template <class V>
+__global__ void __launch_bounds__(kBlock) k_from_canonical(PcgArgs P, const double *src, V *dst) {
+  LEAF_LOOP(P) { dst[b * 64u + m] = V(src[uint32_t(P.canon[b]) * 64u + m]); }
+}
+
+// ---------------------------------------------------------------------------
+// null space (no Dirichlet face): the residual is shifted to zero mean over
+// the active cells after it is formed (Section 2.2)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_sum_active(PcgArgs P, const double *v) {
+  double part = 0.0;
+  LEAF_LOOP(P) {
+    const BrickMeta M = P.T.meta[b];
+    if ((act_mask(M) >> m) & 1ull) part += v[b * 64u + m];
+  }
+  Scalars *S = P.S;
+  block_reduce_finish(part, P.partials, &S->ticket[1], [&](double tot) { S->sum = tot; });
+}
+
+// v -= sum / n_active on active cells and ||v||^2; mode 0: initial residual
+// (sets rr0, tolerance, done), 1: iteration residual (stop test), 2: true
+// residual (tr), 3: solution (no norm)
+template <class V>
+__global__ void __launch_bounds__(kBlock) k_shift_mean(PcgArgs P, double *v, V *v_low,
+                                                       double n_active, int mode, double rtol) {
+  if (mode == 1 && P.S->done) return;
+  double mean = P.S->sum / n_active;
+  double part = 0.0;
+  LEAF_LOOP(P) {
+    const BrickMeta M = P.T.meta[b];
+    uint32_t i = b * 64u + m;
+    double x = ((act_mask(M) >> m) & 1ull) ? v[i] - mean : 0.0;
+    v[i] = x;
+    if (v_low) v_low[i] = V(x);
+    part += x * x;
+  }
+  Scalars *S = P.S;
+  block_reduce_finish(part, P.partials, &S->ticket[2], [&](double tot) {
+    if (mode == 0) {
+      S->rr0 = tot;
+      S->rr = tot;
+      S->tol2 = rtol * rtol * tot;
+      S->done = (tot == 0.0) || !(tot < INFINITY);
+      if (!(tot < INFINITY)) S->status = -5;
+      P.hist[0] = tot > 0.0 ? 1.0 : 0.0;
+    } else if (mode == 1) {
+      S->rr = tot;
+      S->iters += 1;
+      P.hist[S->iters] = S->rr0 > 0.0 ? sqrt(tot / S->rr0) : 0.0;
+      if (!(tot < INFINITY)) {
+        S->status = -5;
+        S->done = 1;
+      } else if (tot <= S->tol2) {
+        S->done = 1;
+      }
+    } else if (mode == 2) {
+      S->tr = tot;
+    }
+  });
+}
+
+// t = rhs - A X over active cells (device order), rhs canonical
+__global__ void __launch_bounds__(kBlock) k_residual_vec(PcgArgs P, const double *rhs,
+                                                         const double *X, double *t) {
+  LEAF_LOOP(P) {
+    const BrickMeta M = P.T.meta[b];
+    double c, k0, k1, k2;
+    leaf_cell(P, b, m, c, k0, k1, k2);
+    double y = composite_Au(P.T, P.C, P.TC, X, M, m, X[b * 64u + m], c, k0, k1, k2);
+    bool act = (act_mask(M) >> m) & 1ull;
+    t[b * 64u + m] = act ? rhs[uint32_t(P.canon[b]) * 64u + m] - y : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-face gradient of the adjoint: dL/dbeta_f = -lambda^T (dA/dbeta_f) p
+// (canonical face and leaf order)
+// ---------------------------------------------------------------------------
+struct GradArgs {
+  const int64_t *owner;
+  const int64_t *other;
+  const int8_t *dir;
+  const int8_t *kind;         // 0 wall, 1 same level, 2 T-junction (owner finer)
+  const int8_t *level;        // per canonical leaf brick
+  const uint64_t *act;        // per canonical leaf brick
+  const double *lam;
+  const double *p;
+  int bc[6];
+  double theta;
+  int64_t n_faces;
+  double *g;
+};
+
+__device__ __forceinline__ bool canon_active(const GradArgs &A, int64_t cell) {
+  return (A.act[cell >> 6] >> (cell & 63)) & 1ull;
+}
+
+__global__ void k_face_gradient(GradArgs A) {
+  int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (f >= A.n_faces) return;
+  int64_t o = A.owner[f];
+  int64_t t = A.other[f];
+  int k = A.kind[f];
+  double h = ldexp(1.0, -int(A.level[o >> 6]));
+  double g = 0.0;
+  bool ao = canon_active(A, o);
+  if (k == 0) {
+    if (ao && A.bc[A.dir[f]] == 1) g = -(h / A.theta) * A.lam[o] * A.p[o];
+  } else if (ao && canon_active(A, t)) {
+    if (k == 1) {
+      g = -h * (A.lam[o] - A.lam[t]) * (A.p[o] - A.p[t]);
+    } else {
+      // mean of p over the active siblings of the fine owner
+      int64_t base = o & ~int64_t(7);
+      double s = 0.0;
+      int n = 0;
+      for (int q = 0; q < 8; ++q)
+        if (canon_active(A, base + q)) {
+          s += A.p[base + q];
+          ++n;
+        }
+      double pbar = n ? s / double(n) : 0.0;
+      g = -(h / 2.0) * (A.lam[o] - A.lam[t]) * (pbar - A.p[t]);
+    }
+  }
+  A.g[f] = g;
+}
+
+// activity masks in canonical leaf-brick order
+__global__ void k_canonical_act(const BrickMeta *meta, const int32_t *canon, uint32_t nlb,
+                                uint64_t *out) {
+  uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nlb) out[canon[b]] = act_mask(meta[b]);
+}
+
+}  // namespace mfmg

@@ -1,0 +1,119 @@
+"""GPU parity of the adjoint path: the transposed cycle M^T, the adjoint
+solve A^T lambda = dL/dp and the per-face gradient, against the oracle, plus
+central finite differences (difference solves) on a cut-cell octree."""
+
+import numpy as np
+import pytest
+
+import problems
+from gpu_fixtures import Case, rel
+from oracle import discretize as D
+from oracle import krylov as K
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", params=["cut_sphere_4_6", "sphere_band_4_6"])
+def case(request):
+    print(f"\n[case {request.param}]", flush=True)
+    if request.param == "cut_sphere_4_6":
+        return Case(5, problems.config_spec(5, 4, 6))
+    return Case(2, problems.config_spec(2, 4, 6))
+
+
+def _loss_grad(case, p):
+    pt = problems.adjoint_target(case.T.level, case.T.ijk, np.abs(p).max())
+    return np.where(case.disc.active, 2.0 * (p - pt), 0.0), pt
+
+
+def test_transposed_cycle_matches_oracle(case):
+    from paper_2604_18886_amd import mfmg
+    h = case.gpu_hierarchy()
+    rng = np.random.default_rng(21)
+    r = np.where(case.disc.active, rng.uniform(-1, 1, case.T.n), 0.0)
+    z = mfmg.apply_precond(h, case.device(r), transpose=True).cpu().numpy()
+    want = case.hier.vcycle_T(r)
+    assert rel(z, want) <= 1e-12
+    # adjoint identity on the device: x . M y == y . M^T x
+    y = np.where(case.disc.active, rng.uniform(-1, 1, case.T.n), 0.0)
+    My = mfmg.apply_precond(h, case.device(y)).cpu().numpy()
+    MTx = mfmg.apply_precond(h, case.device(r), transpose=True).cpu().numpy()
+    assert abs(r @ My - y @ MTx) <= 1e-12 * (abs(r @ My) + abs(y @ MTx))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_adjoint_solve_and_gradient(case, precision):
+    from paper_2604_18886_amd import mfmg
+    h = case.gpu_hierarchy(precision=precision)
+    p_d, st = mfmg.pcg_solve(h, case.device(case.rhs), rtol=1e-12)
+    p = p_d.cpu().numpy()
+    g, _ = _loss_grad(case, p)
+    lam_d, grad_d, ast = mfmg.pcg_solve_adjoint(h, p_d, case.device(g), rtol=1e-12)
+    lam = lam_d.cpu().numpy()
+    grad = grad_d.cpu().numpy()
+    lam_o, info = K.pcg(case.disc.A.T.tocsr(), g, case.hier.vcycle_T, 1e-13, 400,
+                        active=case.disc.active)
+    grad_o = case.disc.face_gradient(lam_o, p)
+    print(f"  precision={precision} adjoint iters={ast['iters']} oracle={info['iters']} "
+          f"true={ast['rel_resid_true']:.2e} lam err={rel(lam, lam_o):.2e} "
+          f"grad err={rel(grad, grad_o):.2e}", flush=True)
+    assert ast["status"] == 0 and ast["rel_resid_true"] <= 1.5e-12
+    assert rel(lam, lam_o) <= 1e-9
+    assert np.abs(grad - grad_o).max() <= 1e-9 * np.abs(grad_o).max()
+    if precision == 0:
+        _, info12 = K.pcg(case.disc.A.T.tocsr(), g, case.hier.vcycle_T, 1e-12, 400,
+                          active=case.disc.active)
+        assert abs(ast["iters"] - info12["iters"]) <= 1
+
+
+def test_gradient_against_finite_differences():
+    """Central FD of L = ||p - p_t||^2 (eps = 1e-6, difference solves in the
+    oracle) on seeded faces, half of them T-junction or cut faces."""
+    from paper_2604_18886_amd import mfmg
+    case = Case(5, problems.config_spec(5, 3, 5))
+    d = case.disc
+    h = case.gpu_hierarchy()
+    p_d, _ = mfmg.pcg_solve(h, case.device(case.rhs), rtol=1e-13)
+    p = p_d.cpu().numpy()
+    g, pt = _loss_grad(case, p)
+    _, grad_d, _ = mfmg.pcg_solve_adjoint(h, p_d, case.device(g), rtol=1e-13)
+    grad = grad_d.cpu().numpy()
+    both = d.active[d.face_owner] & ((d.face_other < 0) | d.active[np.maximum(d.face_other, 0)])
+    special = np.nonzero(((d.face_kind == D.COARSE) | (case.beta < 1)) & both)[0]
+    faces = problems.sample_faces(d.n_faces, special, count=16)
+    faces = faces[both[faces]]
+
+    def factory(bb):
+        dd = D.Discretization(case.T, None, case.bc, case.theta)
+        dd.set_beta(bb)
+        return dd
+    from oracle import multigrid as M
+    fd = K.fd_gradient(factory, case.beta, p, pt, faces, eps=1e-6, rtol=1e-13,
+                       precond_factory=lambda dd: M.Hierarchy(dd).vcycle)
+    ga = grad[faces]
+    denom = np.maximum(np.abs(fd), 1e-8 * np.abs(fd).max())
+    err = np.max(np.abs(ga - fd) / denom)
+    print(f"  FD check on {len(faces)} faces: max rel err {err:.2e}", flush=True)
+    assert err <= 1e-6
+
+
+def test_autograd_function_matches_adjoint():
+    """MFMGSolve.apply: backward of L = ||p - p_t||^2 gives the adjoint's
+    dL/dbeta and dL/drhs = lambda (checked against the oracle)."""
+    import torch
+    from paper_2604_18886_amd import autograd
+    case = Case(5, problems.config_spec(5, 3, 5))
+    beta = torch.tensor(case.beta, dtype=torch.float64, device="cuda", requires_grad=True)
+    rhs = torch.tensor(case.rhs, dtype=torch.float64, device="cuda", requires_grad=True)
+    p = autograd.solve(beta, rhs, case.tree, case.bc, case.theta, rtol=1e-12)
+    pn = p.detach().cpu().numpy()
+    g, pt = _loss_grad(case, pn)
+    pt_d = torch.tensor(pt, dtype=torch.float64, device="cuda")
+    act = torch.tensor(case.disc.active, device="cuda")
+    loss = (((p - pt_d) ** 2) * act).sum()
+    loss.backward()
+    lam_o, _ = K.pcg(case.disc.A.T.tocsr(), g, case.hier.vcycle_T, 1e-13, 400,
+                     active=case.disc.active)
+    gr_o = case.disc.face_gradient(lam_o, pn)
+    assert rel(rhs.grad.cpu().numpy(), lam_o) <= 1e-9
+    assert np.abs(beta.grad.cpu().numpy() - gr_o).max() <= 1e-9 * np.abs(gr_o).max()

@@ -113,3 +113,28 @@ def test_solve_matches_oracle(case, precision):
                            rtol=1e-6, atol=1e-14)
     # inactive leaves are zero on output
     assert np.all(p[~case.disc.active] == 0.0)
+
+
+def test_null_space_all_neumann():
+    """All walls Neumann and no solid: the residual is shifted to zero mean
+    (Section 2.2); the zero-mean solution matches the oracle's."""
+    import problems
+    from gpu_fixtures import Case
+    from oracle import krylov as K
+    from paper_2604_18886_amd import mfmg
+    spec = problems.config_spec(2, 3, 5)
+    rng = np.random.default_rng(12)
+    case = Case(2, spec, bc=(0,) * 6, theta=0.5)
+    act = case.disc.active
+    rhs = np.where(act, rng.uniform(-1, 1, case.T.n), 0.0)
+    rhs[act] -= rhs[act].mean()
+    h = case.gpu_hierarchy()
+    p, st = mfmg.pcg_solve(h, case.device(rhs), rtol=1e-10)
+    p = p.cpu().numpy()
+    x, info = K.pcg(case.disc.A, rhs, case.hier.vcycle, 1e-13, 400, null_space=True,
+                    active=act)
+    print(f"  null space: gpu iters={st['iters']} oracle iters={info['iters']} "
+          f"err={rel(p, x):.2e}", flush=True)
+    assert st["status"] == 0
+    assert abs(p[act].mean()) <= 1e-12 * np.abs(p).max()
+    assert rel(p, x) <= 1e-9
