@@ -104,7 +104,7 @@ def solve_and_grad(disc, hier, rhs, loss_grad, rtol=1e-10, max_iter=200):
 
 
 def fd_gradient(disc_factory, beta, p, p_target, faces, eps=1e-6, rtol=1e-13,
-                precond_factory=None, max_iter=400):
+                precond_factory=None, max_iter=400, rhs=None):
     """Central finite differences of L = sum_active (p - p_t)^2 with respect to
     beta_f, computed as difference solves so that cancellation does not
     destroy the O(eps) change of L:
@@ -114,24 +114,30 @@ def fd_gradient(disc_factory, beta, p, p_target, faces, eps=1e-6, rtol=1e-13,
 
     where p is the base solution; then g_f = (dL_+ - dL_-) / (2 eps).
     ``disc_factory(beta)`` returns a Discretization for coefficients beta.
-    The base residual r0 is dropped: p is solved to tight tolerance and
-    r0 contributes only at second order after the central difference."""
+    Every face coefficient of Eq. (3) is proportional to beta (and the
+    coarse side of a T-face is a sum of such), so A is linear in beta and
+    (dA/dbeta_f) p = (A(beta + e_f) - A(beta)) p exactly; forming it with a
+    unit step keeps the cancellation of the two products at the level of
+    the operator, not of eps.  ``rhs`` (optional) gives r0; without it r0
+    is taken as 0 (p solved to tight tolerance)."""
     out = np.zeros(len(faces))
-    base_Ap = disc_factory(beta).A @ p
+    base = disc_factory(beta)
+    base_Ap = base.A @ p
+    r0 = np.zeros_like(p) if rhs is None else np.where(base.active, rhs - base_Ap, 0.0)
     for n, f in enumerate(faces):
+        bu = beta.copy()
+        bu[f] = bu[f] + 1.0
+        dA_p = disc_factory(bu).A @ p - base_Ap
         dls = []
         for sgn in (+1.0, -1.0):
             bb = beta.copy()
             bb[f] = bb[f] + sgn * eps
             dpert = disc_factory(bb)
             act = dpert.active
-            # (A(beta + s eps e_f) - A(beta)) p, formed exactly as a difference
-            # of the two assembled operators applied to p
-            dA_p = dpert.A @ p - base_Ap
-            rhs = np.where(act, -dA_p, 0.0)
+            b = np.where(act, r0 - sgn * eps * dA_p, 0.0)
             M = precond_factory(dpert) if precond_factory else None
             # the difference solve is a forward solve with A(beta +- eps e_f)
-            dp, _ = pcg(dpert.A, rhs, M, rtol, max_iter, active=act)
+            dp, _ = pcg(dpert.A, b, M, rtol, max_iter, active=act)
             e = np.where(act, p - p_target, 0.0)
             dls.append(2.0 * e @ dp + dp @ dp)
         out[n] = (dls[0] - dls[1]) / (2.0 * eps)

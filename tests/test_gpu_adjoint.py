@@ -66,13 +66,15 @@ def test_adjoint_solve_and_gradient(case, precision):
         assert abs(ast["iters"] - info12["iters"]) <= 1
 
 
-def test_gradient_against_finite_differences():
+@pytest.mark.parametrize("precision", [0, 1])
+def test_gradient_against_finite_differences(precision):
     """Central FD of L = ||p - p_t||^2 (eps = 1e-6, difference solves in the
-    oracle) on seeded faces, half of them T-junction or cut faces."""
+    oracle) on 50 seeded faces, half of them T-junction or cut faces, for the
+    FP64 and the mixed-precision cycle as preconditioner."""
     from paper_2604_18886_amd import mfmg
     case = Case(5, problems.config_spec(5, 3, 5))
     d = case.disc
-    h = case.gpu_hierarchy()
+    h = case.gpu_hierarchy(precision=precision)
     p_d, _ = mfmg.pcg_solve(h, case.device(case.rhs), rtol=1e-13)
     p = p_d.cpu().numpy()
     g, pt = _loss_grad(case, p)
@@ -80,7 +82,7 @@ def test_gradient_against_finite_differences():
     grad = grad_d.cpu().numpy()
     both = d.active[d.face_owner] & ((d.face_other < 0) | d.active[np.maximum(d.face_other, 0)])
     special = np.nonzero(((d.face_kind == D.COARSE) | (case.beta < 1)) & both)[0]
-    faces = problems.sample_faces(d.n_faces, special, count=16)
+    faces = problems.sample_faces(d.n_faces, special, count=50)
     faces = faces[both[faces]]
 
     def factory(bb):
@@ -89,7 +91,7 @@ def test_gradient_against_finite_differences():
         return dd
     from oracle import multigrid as M
     fd = K.fd_gradient(factory, case.beta, p, pt, faces, eps=1e-6, rtol=1e-13,
-                       precond_factory=lambda dd: M.Hierarchy(dd).vcycle)
+                       precond_factory=lambda dd: M.Hierarchy(dd).vcycle, rhs=case.rhs)
     ga = grad[faces]
     denom = np.maximum(np.abs(fd), 1e-8 * np.abs(fd).max())
     err = np.max(np.abs(ga - fd) / denom)

@@ -68,7 +68,7 @@ def test_adjoint_gradient_matches_difference_solve_fd():
         dd.set_beta(bb)
         return dd
     fd = K.fd_gradient(factory, beta, p, pt, faces, eps=1e-6, rtol=1e-13,
-                       precond_factory=lambda dd: hierarchy(dd).vcycle)
+                       precond_factory=lambda dd: hierarchy(dd).vcycle, rhs=rhs)
     ga = g[faces]
     denom = np.maximum(np.abs(fd), 1e-8 * np.abs(fd).max())
     assert np.max(np.abs(ga - fd) / denom) <= 1e-6
