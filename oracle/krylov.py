@@ -119,7 +119,14 @@ def fd_gradient(disc_factory, beta, p, p_target, faces, eps=1e-6, rtol=1e-13,
     (dA/dbeta_f) p = (A(beta + e_f) - A(beta)) p exactly; forming it with a
     unit step keeps the cancellation of the two products at the level of
     the operator, not of eps.  ``rhs`` (optional) gives r0; without it r0
-    is taken as 0 (p solved to tight tolerance)."""
+    is taken as 0 (p solved to tight tolerance).
+
+    The step is relative to the coupling of the face's cells: eps_f = eps *
+    min(1, c_i / (dc_i/dbeta_f)) over the face's cells i.  At a nearly solid
+    cell (all face fractions ~1e-4) a fixed step of 1e-6 would change its
+    operator by ~1% and the O(eps^2) error of the central difference would
+    dominate; elsewhere c_i / (dc_i/dbeta_f) is the sum of the cell's face
+    betas (about 6) and eps_f = eps.  Returns g_f."""
     out = np.zeros(len(faces))
     base = disc_factory(beta)
     base_Ap = base.A @ p
@@ -127,18 +134,22 @@ def fd_gradient(disc_factory, beta, p, p_target, faces, eps=1e-6, rtol=1e-13,
     for n, f in enumerate(faces):
         bu = beta.copy()
         bu[f] = bu[f] + 1.0
-        dA_p = disc_factory(bu).A @ p - base_Ap
+        du = disc_factory(bu)
+        dA_p = du.A @ p - base_Ap
+        cells = [base.face_owner[f]] + ([base.face_other[f]] if base.face_other[f] >= 0 else [])
+        ratio = [base.c[i] / (du.c[i] - base.c[i]) for i in cells if du.c[i] != base.c[i]]
+        step = eps * min([1.0] + ratio)
         dls = []
         for sgn in (+1.0, -1.0):
             bb = beta.copy()
-            bb[f] = bb[f] + sgn * eps
+            bb[f] = bb[f] + sgn * step
             dpert = disc_factory(bb)
             act = dpert.active
-            b = np.where(act, r0 - sgn * eps * dA_p, 0.0)
+            b = np.where(act, r0 - sgn * step * dA_p, 0.0)
             M = precond_factory(dpert) if precond_factory else None
             # the difference solve is a forward solve with A(beta +- eps e_f)
             dp, _ = pcg(dpert.A, b, M, rtol, max_iter, active=act)
             e = np.where(act, p - p_target, 0.0)
             dls.append(2.0 * e @ dp + dp @ dp)
-        out[n] = (dls[0] - dls[1]) / (2.0 * eps)
+        out[n] = (dls[0] - dls[1]) / (2.0 * step)
     return out
