@@ -12,6 +12,12 @@ hierarchy are built beforehand.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
+Counter passes for the HBM traffic of the finest half-sweep (each under its
+own `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` run):
+
+    python bench.py --traffic-pass          # smoother launches + a plain copy
+    python bench.py --summarize-pmc FETCH.csv WRITE.csv
+
 Prints one JSON line.  `value` is the mixed-precision solve rate (FP32
 cycle with FP16 inner coefficients inside FP64 PCG) in million active leaf
 cells per second; the FP64 solve rate is reported beside it.
@@ -58,6 +64,49 @@ def measured_traffic(precision_name, level):
     return rec["hbm_bytes_per_launch"]
 
 
+COPY_BYTES = 1 << 30      # plain copy used to scale the counters
+TRAFFIC_REPS = 4
+
+
+def summarize_pmc(fetch_csv, write_csv, level):
+    """HBM bytes per launch of the finest mixed half-sweep from two rocprofv3
+    counter_collection.csv files (FETCH_SIZE, WRITE_SIZE in KiB per dispatch),
+    each scaled by what the same counter reads for a plain copy of
+    COPY_BYTES bytes."""
+    import csv
+
+    def per_kernel(path, counter):
+        rows = {}
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r.get("Counter_Name") != counter:
+                    continue
+                rows.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
+        return rows
+
+    out = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = per_kernel(path, counter)
+        smooth = [v for k, v in rows.items() if "k_smooth" in k]
+        copy = [v for k, v in rows.items() if "copy" in k.lower() or "elementwise" in k]
+        if not smooth or not copy:
+            raise SystemExit(f"{path}: no k_smooth or copy dispatches for {counter}")
+        smooth = smooth[0]
+        copy = max(copy, key=lambda v: sum(v) / len(v))
+        factor = (sum(copy) / len(copy)) / COPY_BYTES
+        out[counter] = {"per_launch_bytes_raw": sum(smooth) / len(smooth),
+                        "launches": len(smooth), "copy_raw_bytes": sum(copy) / len(copy),
+                        "copy_factor": factor,
+                        "per_launch_bytes": sum(smooth) / len(smooth) / factor}
+    rec = {"source_hash": kernel_source_hash(), "level": level,
+           "fetch_bytes_per_launch": out["FETCH_SIZE"]["per_launch_bytes"],
+           "write_bytes_per_launch": out["WRITE_SIZE"]["per_launch_bytes"],
+           "hbm_bytes_per_launch": (out["FETCH_SIZE"]["per_launch_bytes"]
+                                    + out["WRITE_SIZE"]["per_launch_bytes"]),
+           "counters": out}
+    return rec
+
+
 def cpu_baseline(sample_levels=(5, 8)):
     """The oracle (test infrastructure) timed on the host, one thread, on a
     smaller member of the same workload family."""
@@ -95,10 +144,21 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", type=int, default=4, choices=[1, 2, 3, 4])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic-pass", action="store_true",
+                    help="only the finest mixed half-sweep and a plain copy (counter runs)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     args = ap.parse_args()
+    if args.summarize_pmc:
+        spec = __import__("problems").config_spec(args.workload)
+        rec = summarize_pmc(*args.summarize_pmc, spec["max_level"])
+        path = os.path.join(ROOT, "profiles", "traffic_smooth_large_workload.json")
+        with open(path, "w") as fh:
+            json.dump({"mixed": rec}, fh, indent=1)
+        print(json.dumps(rec))
+        return
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the solver "
-              "has no multi-GPU path in this build", file=sys.stderr)
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): the solver is "
+              "single-GPU; how it would shard is described with the design", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -132,12 +192,23 @@ def main():
     t0 = time.perf_counter()
     co = mfmg.assemble_coeffs(tree, beta_d, bc, theta)
     nact = int((co.leaf_coeffs()[0] != 0).sum().item())
+    L = spec["max_level"]
+    if args.traffic_pass:
+        h = mfmg.build_hierarchy(co, precision=mfmg.MIXED)
+        ms, by = mfmg.profile(h, mfmg.PROFILE_SMOOTH, L, reps=TRAFFIC_REPS)
+        src = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(TRAFFIC_REPS):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] traffic pass: {TRAFFIC_REPS} half-sweeps at level {L} "
+            f"({by:.3e} algorithmic bytes each), {TRAFFIC_REPS} copies of {COPY_BYTES} bytes")
+        return
     hiers = {"mixed": mfmg.build_hierarchy(co, precision=mfmg.MIXED),
              "fp64": mfmg.build_hierarchy(co, precision=mfmg.FP64)}
     torch.cuda.synchronize()
     log(f"[bench] {nact} active leaves; coefficients + hierarchies in "
         f"{time.perf_counter() - t0:.1f} s")
-    L = spec["max_level"]
     out = {}
     p = torch.empty_like(rhs_d)
     for name, h in hiers.items():

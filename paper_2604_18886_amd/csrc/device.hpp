@@ -1,5 +1,5 @@
 // Device-side helpers shared by the solver's HIP kernels: brick addressing,
-// wavefront shuffles and deterministic block reductions.
+// wavefront shuffles, buffer access and the solve's device-resident scalars.
 #pragma once
 
 #include <hip/hip_fp16.h>
@@ -75,6 +75,59 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// ---------------------------------------------------------------------------
+// Raw buffer access: a per-lane element offset (voffset) plus a wave-uniform
+// element base (soffset), both 32-bit, against a wave-uniform resource
+// descriptor.  The per-brick part of an address is then scalar arithmetic
+// and the per-lane part a loop-invariant register.  Every buffer accessed
+// this way is below 4 GiB (checked on the host).
+// ---------------------------------------------------------------------------
+constexpr int kRsrcWord3 = 0x00020000;  // raw (untyped, unswizzled) buffer, gfx9 family
+constexpr uint64_t kMaxBufferBytes = 0xffffffffull;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint64_t bytes) {
+  uint32_t n = bytes >= kMaxBufferBytes ? uint32_t(kMaxBufferBytes) : uint32_t(bytes);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, int(n), kRsrcWord3);
+}
+
+template <class T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, uint32_t lane, uint32_t base);
+template <>
+__device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, uint32_t lane,
+                                              uint32_t base) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_raw_buffer_load_b32(r, int(lane * 4u), int(base * 4u), 0));
+}
+template <>
+__device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, uint32_t lane,
+                                                uint32_t base) {
+  return __builtin_bit_cast(
+      double, __builtin_amdgcn_raw_buffer_load_b64(r, int(lane * 8u), int(base * 8u), 0));
+}
+template <>
+__device__ __forceinline__ __half bload<__half>(__amdgpu_buffer_rsrc_t r, uint32_t lane,
+                                                uint32_t base) {
+  return __builtin_bit_cast(
+      __half, __builtin_amdgcn_raw_buffer_load_b16(r, int(lane * 2u), int(base * 2u), 0));
+}
+
+template <class T>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t lane, uint32_t base,
+                                       T v);
+template <>
+__device__ __forceinline__ void bstore<float>(__amdgpu_buffer_rsrc_t r, uint32_t lane,
+                                              uint32_t base, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, int(lane * 4u),
+                                        int(base * 4u), 0);
+}
+template <>
+__device__ __forceinline__ void bstore<double>(__amdgpu_buffer_rsrc_t r, uint32_t lane,
+                                               uint32_t base, double v) {
+  typedef unsigned u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned))));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, int(lane * 8u),
+                                        int(base * 8u), 0);
+}
+
 // Scalars of one PCG solve, resident in device memory.
 struct Scalars {
   double rr0;    // ||r_0||^2
@@ -91,46 +144,6 @@ struct Scalars {
   int status;    // 0 running/converged, -5 breakdown
   int iters;
   int pad;
-  unsigned int ticket[4];  // last-block counters of the reductions
 };
-
-// Deterministic two-stage sum: every block stores its partial, the last
-// block to finish adds all partials in index order and calls fin(total).
-template <class Fin>
-__device__ __forceinline__ void block_reduce_finish(double v, double *partials,
-                                                    unsigned int *ticket, Fin fin) {
-  __shared__ double red[kWavesPerBlock];
-  __shared__ bool last;
-  v = wave_sum(v);
-  int lane = threadIdx.x & (kWave - 1);
-  int w = threadIdx.x / kWave;
-  if (lane == 0) red[w] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int i = 0; i < kWavesPerBlock; ++i) s += red[i];
-    partials[blockIdx.x] = s;
-    __threadfence();
-    unsigned int t = atomicAdd(ticket, 1u);
-    last = (t == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  double s = 0.0;
-  for (unsigned int i = threadIdx.x; i < gridDim.x; i += blockDim.x) {
-    s += partials[i];
-  }
-  // fixed-order combination across the block
-  s = wave_sum(s);
-  if (lane == 0) red[w] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double tot = 0.0;
-    for (int i = 0; i < kWavesPerBlock; ++i) tot += red[i];
-    *ticket = 0u;
-    fin(tot);
-  }
-}
 
 }  // namespace mfmg

@@ -52,6 +52,17 @@ struct Range {
   __host__ __device__ uint32_t n() const { return n_leaf + n_inner; }
 };
 
+// Brick records are never written by a kernel that reads them: loading them
+// through the constant address space lets a wave-uniform load be a scalar
+// load even after the kernel has stored to other arrays.
+__device__ __forceinline__ BrickMeta load_meta(const BrickMeta *meta, uint32_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return ((const __attribute__((address_space(4))) BrickMeta *)meta)[b];
+#else
+  return meta[b];  // host pass: never executed
+#endif
+}
+
 __device__ __forceinline__ uint32_t wave_id() {
   return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 }
@@ -109,62 +120,6 @@ __device__ __forceinline__ int coarse_local(const BrickMeta &M, int m, int d,
     c[ax] = ((g >> 1) - MJ.coord[ax] * 4) & 3;
   }
   return dev_morton(c[0], c[1], c[2]);
-}
-
-// ---------------------------------------------------------------------------
-// Neighbour sum of the level operator at one cell (every lane of the wave
-// executes this for its own cell of brick b):
-//   S_m = sum_d k_d v_d,   (A u)_m = c_m u_m - S_m,
-// v_d the same-level neighbour value, 0 at a wall, or at a T-junction the
-// ghost u_m + (u_J - mean_active_siblings(u)) / 2 with u_J read from the
-// coarser level.  All neighbour loads are issued before any arithmetic; the
-// T-junction work sits behind a wave-uniform branch on the face flags.
-// ---------------------------------------------------------------------------
-template <class V, class CL, class CI>
-__device__ __forceinline__ V neighbour_sum(const Topo &T, const Coefs<V, CL, CI> &cf,
-                                           const V *__restrict__ U, const BrickMeta &M,
-                                           int m, V u, V k0, V k1, V k2) {
-  V v[6], k[6];
-#pragma unroll
-  for (int d = 0; d < 6; ++d) {
-    int a = d >> 1;
-    int p = dev_partner(m, d);
-    V kown = a == 0 ? k0 : (a == 1 ? k1 : k2);
-    v[d] = shfl(u, p);
-    k[d] = (d & 1) ? shfl(kown, p) : kown;
-  }
-#pragma unroll
-  for (int d = 0; d < 6; ++d) {
-    int p = dev_partner(m, d);
-    if (dev_outside(m, d) && M.nbr[d] >= 0) {
-      v[d] = U[uint32_t(M.nbr[d]) * 64u + p];
-      if (d & 1) k[d] = cf.get(uint32_t(M.nbr[d]), 1 + (d >> 1), p);
-    }
-  }
-#pragma unroll
-  for (int d = 0; d < 6; ++d)
-    if (dev_outside(m, d) && ((M.flags >> (16 + d)) & 1u)) v[d] = V(0);
-  if (M.flags & kFlagT) {
-    uint64_t amask = act_mask(M);
-    bool act = (amask >> m) & 1ull;
-    V s = group8_sum(act ? u : V(0));
-    int cnt = __popcll((amask >> (m & 56)) & 0xffull);
-    V ubar = cnt ? s / V(cnt) : V(0);
-#pragma unroll
-    for (int d = 0; d < 6; ++d) {
-      if (((M.flags >> d) & 1u) && dev_outside(m, d)) {
-        int32_t J = dev_decode_coarse(M.nbr[d]);
-        const BrickMeta MJ = T.meta[J];
-        V uJ = U[uint32_t(J) * 64u + coarse_local(M, m, d, MJ)];
-        v[d] = u + (uJ - ubar) * V(0.5);
-        if (d & 1) k[d] = cf.tplus(M.tplus, d >> 1, dev_face_index(m, d >> 1));
-      }
-    }
-  }
-  V acc = V(0);
-#pragma unroll
-  for (int d = 0; d < 6; ++d) acc += k[d] * v[d];
-  return acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -314,13 +269,50 @@ __global__ void __launch_bounds__(kBlock) k_convert_inner(const double *coef, To
         __float2half_rn(float(coef[b * 256u + comp * 64 + m] * inv_h));
 }
 
+// Plus-face coefficients of every brick, for the level kernels: entry
+// a * 16 + f is the coefficient of the face between the brick's cell on its
+// +a side with face index f and what lies beyond it -- the same-level
+// neighbour's k_a (in mixed precision rounded exactly as the neighbour's own
+// coefficients are stored), the T-face coefficient K_F, or 0 at a wall.
+template <class CL>
+__global__ void __launch_bounds__(kBlock) k_plus_faces(Topo T, const double *coef,
+                                                       const double *tc, CL *pf, int half_inner) {
+  uint32_t b = blockIdx.x * kWavesPerBlock + wave_id();
+  int e = threadIdx.x & (kWave - 1);
+  if (b >= T.nb || e >= 48) return;
+  int a = e >> 4, f = e & 15;
+  int c[3];
+  c[a] = 3;
+  c[a == 0 ? 1 : 0] = f & 3;
+  c[a == 2 ? 1 : 2] = f >> 2;
+  int m = dev_morton(c[0], c[1], c[2]);
+  int d = 2 * a + 1;
+  const BrickMeta M = T.meta[b];
+  int32_t n = M.nbr[d];
+  double v = 0.0;
+  if (n >= 0) {
+    v = coef[uint32_t(n) * 256u + (1 + a) * 64 + dev_partner(m, d)];
+    if (half_inner && uint32_t(n) >= T.nlb) {
+      float hv = __half2float(__float2half_rn(float(v * ldexp(1.0, M.level))));
+      v = double(hv * ldexpf(1.0f, -M.level));
+    }
+  } else if ((M.flags >> d) & 1u) {
+    v = tc[uint32_t(M.tplus) * 48u + a * 16 + f];
+  }
+  pf[b * 48u + e] = CL(v);
+}
+
 // ---------------------------------------------------------------------------
-// multigrid cycle kernels (one wave per brick of a level)
+// multigrid cycle kernels.  A wave processes one brick at a time and loops
+// over the bricks of a level; everything that depends only on the lane is
+// computed once, outside the loop, and every per-brick address is scalar
+// arithmetic (buffer loads with a uniform base).
 // ---------------------------------------------------------------------------
 template <class V, class CL, class CI>
 struct LevelArgs {
   Topo T;
   Coefs<V, CL, CI> cf;
+  const CL *pf;      // plus-face coefficients, 48 per brick (k_plus_faces)
   V *U;              // iterate, nb * 64
   V *B;              // right-hand side, nb * 64 (leaf part: the PCG residual)
   V *Ustar;          // FAS initial guess of inner cells, (nb - nlb) * 64
@@ -328,65 +320,252 @@ struct LevelArgs {
   const int *done;   // skip when the solve has stopped
 };
 
-template <class V, class CL, class CI>
-__device__ __forceinline__ void load_cell(const LevelArgs<V, CL, CI> &A, uint32_t b, int m, V &c,
-                                          V &k0, V &k1, V &k2) {
-  c = A.cf.get(b, 0, m);
-  k0 = A.cf.get(b, 1, m);
-  k1 = A.cf.get(b, 2, m);
-  k2 = A.cf.get(b, 3, m);
+// A voffset at or above this is out of range for every buffer the level
+// kernels read (all are below 2 GiB): such a load returns 0.
+constexpr uint32_t kOutOfRange = 0x80000000u;
+
+// Lane constants: the lane's cell, its partners across the six directions,
+// and the byte offsets the stencil's loads use.
+template <class V, class CL>
+struct LaneC {
+  uint32_t m;        // local Morton index
+  int p[6];          // partner cell across direction d (this brick or the next)
+  bool out[6];       // the partner lies in the neighbouring brick
+  uint32_t poff[6];  // out[d] ? p * sizeof(V) : kOutOfRange
+  uint32_t foff[3];  // plus-face slot of the cell on axis a, in bytes
+  int colour;        // (x + y + z) & 1
+};
+
+template <class V, class CL>
+__device__ __forceinline__ LaneC<V, CL> lane_consts() {
+  LaneC<V, CL> L;
+  L.m = threadIdx.x & (kWave - 1);
+  int m = int(L.m);
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    L.p[d] = dev_partner(m, d);
+    L.out[d] = dev_outside(m, d);
+    L.poff[d] = L.out[d] ? uint32_t(L.p[d]) * uint32_t(sizeof(V)) : kOutOfRange;
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    L.foff[a] = uint32_t(a * 16 + dev_face_index(m, a)) * uint32_t(sizeof(CL));
+  L.colour = (dev_cx(m) + dev_cy(m) + dev_cz(m)) & 1;
+  return L;
 }
 
-// One colour half-sweep of red-black Gauss-Seidel: on the cells of the
-// colour, u_m = (b_m + S_m) / c_m, i.e. u_m += (b - A u)_m / c_m with every
-// read taken from the values before the sweep.
+// Bricks of a level range for this wave.  Workgroups are dispatched to the
+// eight XCDs in turn (workgroup g on XCD g mod 8); each XCD takes one
+// contiguous eighth of the range, so bricks that are close in Morton order,
+// and hence mostly each other's neighbours, share that XCD's L2.  The grid
+// is a multiple of 8 workgroups.
+struct WaveLoop {
+  uint32_t first, end, step;
+};
+__device__ __forceinline__ WaveLoop wave_loop(uint32_t n) {
+  uint32_t x = blockIdx.x & 7u;
+  uint32_t j = (blockIdx.x >> 3) * kWavesPerBlock + wave_id();
+  uint32_t chunk = (n + 7u) >> 3;
+  uint32_t lo = x * chunk;
+  uint32_t hi = lo + chunk < n ? lo + chunk : n;
+  return {lo + j, hi, (gridDim.x >> 3) * kWavesPerBlock};
+}
+
+template <class V, class CL, class CI>
+struct LevelView {
+  __amdgpu_buffer_rsrc_t u, b, us, cl, ci, pf;
+  const BrickMeta *meta;
+  uint32_t nlb;
+  V iscale;
+};
+
+template <class V, class CL, class CI>
+__device__ __forceinline__ LevelView<V, CL, CI> level_view(const LevelArgs<V, CL, CI> &A) {
+  LevelView<V, CL, CI> X;
+  uint64_t nb = A.T.nb, nlb = A.T.nlb;
+  X.u = make_rsrc(A.U, nb * 64 * sizeof(V));
+  X.b = make_rsrc(A.B, nb * 64 * sizeof(V));
+  X.us = make_rsrc(A.Ustar, (nb - nlb) * 64 * sizeof(V));
+  X.cl = make_rsrc(A.cf.leaf, nlb * 256 * sizeof(CL));
+  X.ci = make_rsrc(A.cf.inner, (nb - nlb) * 256 * sizeof(CI));
+  X.pf = make_rsrc(A.pf, nb * 48 * sizeof(CL));
+  X.meta = A.T.meta;
+  X.nlb = A.T.nlb;
+  X.iscale = A.cf.iscale;
+  return X;
+}
+
+// Coefficient comp (0 = c, 1 + a = k_a) of the lane's cell of brick b;
+// INNER selects the inner-brick array (FP16 in mixed precision, stored
+// divided by the cell size).
+template <bool INNER, class V, class CL, class CI>
+__device__ __forceinline__ V own_coef(const LevelView<V, CL, CI> &X, uint32_t b, int comp,
+                                      uint32_t m) {
+  if constexpr (INNER) {
+    V v = V(bload<CI>(X.ci, m, (b - X.nlb) * 256u + uint32_t(comp) * 64u));
+    if constexpr (std::is_same<CL, CI>::value) return v;
+    else return v * X.iscale;
+  } else {
+    return V(bload<CL>(X.cl, m, b * 256u + uint32_t(comp) * 64u));
+  }
+}
+
+template <class T>
+__device__ __forceinline__ T bload_bytes(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, int(voff), int(soff), 0));
+  else if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, int(voff), int(soff), 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, int(voff), int(soff), 0));
+}
+
+// Neighbour sum of the level operator at the lane's cell of brick b:
+//   S_m = sum_d k_d v_d,   (A u)_m = c_m u_m - S_m,
+// v_d the same-level neighbour value (a lane shuffle inside the brick, a
+// load from the neighbouring brick across its faces), 0 at a wall, or at a
+// T-junction (Eq. 10) the ghost u_m + (u_J - mean of the active siblings)/2
+// with u_J read from the coarser leaf.  k_d is the cell's own k_a on the
+// minus side and the neighbour's k_a on the plus side (a shuffle inside
+// the brick, the brick's plus-face array across its faces).  The loads
+// across a face are issued by every lane with an offset that is out of
+// range for the inner lanes and, at a wall or T-face, for all lanes, so
+// the only branch is a scalar one around the T-junction ghosts.
+template <class V, class CL, class CI>
+__device__ __forceinline__ V stencil_sum(const LevelView<V, CL, CI> &X, const LaneC<V, CL> &L,
+                                         uint32_t b, const BrickMeta &M, V u, V k0, V k1,
+                                         V k2) {
+  V v[6], k[6];
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    int a = d >> 1;
+    V kown = a == 0 ? k0 : (a == 1 ? k1 : k2);
+    int32_t n = M.nbr[d];
+    uint32_t sb = n >= 0 ? uint32_t(n) * uint32_t(64 * sizeof(V)) : kOutOfRange;
+    V vl = bload_bytes<V>(X.u, L.poff[d] + sb, 0);
+    V vs = shfl(u, L.p[d]);
+    v[d] = L.out[d] ? vl : vs;
+    if (d & 1) {
+      V kl = V(bload_bytes<CL>(X.pf, L.foff[a], b * uint32_t(48 * sizeof(CL))));
+      V ks = shfl(kown, L.p[d]);
+      k[d] = L.out[d] ? kl : ks;
+    } else {
+      k[d] = kown;
+    }
+  }
+  if (M.flags & kFlagT) {
+    uint64_t amask = act_mask(M);
+    bool act = (amask >> L.m) & 1ull;
+    V s = group8_sum(act ? u : V(0));
+    int cnt = __popcll((amask >> (L.m & 56u)) & 0xffull);
+    V ubar = cnt ? s / V(cnt) : V(0);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      if ((M.flags >> d) & 1u) {
+        uint32_t J = uint32_t(dev_decode_coarse(M.nbr[d]));
+        const BrickMeta MJ = load_meta(X.meta, J);
+        V uJ = bload<V>(X.u, uint32_t(coarse_local(M, int(L.m), d, MJ)), J * 64u);
+        V g = u + (uJ - ubar) * V(0.5);
+        v[d] = L.out[d] ? g : v[d];
+      }
+    }
+  }
+  V acc = V(0);
+#pragma unroll
+  for (int d = 0; d < 6; ++d) acc += k[d] * v[d];
+  return acc;
+}
+
+// One brick of a colour half-sweep of red-black Gauss-Seidel: on the cells
+// of the colour u_m = (b_m + S_m) / c_m, every read taken before the write
+// (the neighbours of a cell all have the other colour).
+template <bool INNER, class V, class CL, class CI>
+__device__ __forceinline__ void smooth_brick(const LevelView<V, CL, CI> &X, const LaneC<V, CL> &L,
+                                             uint32_t b, int colour) {
+  const BrickMeta M = load_meta(X.meta, b);
+  V c = own_coef<INNER>(X, b, 0, L.m);
+  V k0 = own_coef<INNER>(X, b, 1, L.m);
+  V k1 = own_coef<INNER>(X, b, 2, L.m);
+  V k2 = own_coef<INNER>(X, b, 3, L.m);
+  V u = bload<V>(X.u, L.m, b * 64u);
+  V rhs = bload<V>(X.b, L.m, b * 64u);
+  V S = stencil_sum(X, L, b, M, u, k0, k1, k2);
+  bool act = (act_mask(M) >> L.m) & 1ull;
+  if (act && L.colour == colour) bstore<V>(X.u, L.m, b * 64u, div_by(rhs + S, c));
+}
+
 template <class V, class CL, class CI>
 __global__ void __launch_bounds__(kBlock) k_smooth(LevelArgs<V, CL, CI> A, int colour) {
   if (A.done && *A.done) return;
-  uint32_t i = blockIdx.x * kWavesPerBlock + wave_id();
-  int m = threadIdx.x & (kWave - 1);
-  if (i >= A.R.n()) return;
-  uint32_t b = A.R.brick(i);
-  const BrickMeta M = A.T.meta[b];
-  V c, k0, k1, k2;
-  load_cell(A, b, m, c, k0, k1, k2);
-  V u = A.U[b * 64u + m];
-  V rhs = A.B[b * 64u + m];
-  V S = neighbour_sum(A.T, A.cf, A.U, M, m, u, k0, k1, k2);
-  bool act = (act_mask(M) >> m) & 1ull;
-  int col = (dev_cx(m) + dev_cy(m) + dev_cz(m)) & 1;
-  if (act && col == colour) A.U[b * 64u + m] = div_by(rhs + S, c);
+  const LaneC<V, CL> L = lane_consts<V, CL>();
+  const LevelView<V, CL, CI> X = level_view(A);
+  const WaveLoop W = wave_loop(A.R.n());
+  for (uint32_t i = W.first; i < W.end; i += W.step) {
+    if (i < A.R.n_leaf) smooth_brick<false>(X, L, A.R.leaf_lo + i, colour);
+    else smooth_brick<true>(X, L, A.R.inner_lo + (i - A.R.n_leaf), colour);
+  }
 }
 
-// Residual, restriction and FAS initial guess from level l to its parents:
-//   b_P = beta_mg (1/alpha) sum_children r,  u_P = u*_P = mean of active
-//   children (k_fas_rhs then adds A^{l-1} u* on inner cells).
+// The first half-sweep of a level whose bricks are all leaves, from a zero
+// iterate: every neighbour, ghost and wall value is 0, so the sweep sets
+// u = b / c on the cells of the colour and 0 on all others (which also
+// clears the iterate).
 template <class V, class CL, class CI>
-__global__ void __launch_bounds__(kBlock) k_restrict(LevelArgs<V, CL, CI> A, V scale) {
+__global__ void __launch_bounds__(kBlock) k_smooth_zero(LevelArgs<V, CL, CI> A, int colour) {
   if (A.done && *A.done) return;
-  uint32_t i = blockIdx.x * kWavesPerBlock + wave_id();
-  int m = threadIdx.x & (kWave - 1);
-  if (i >= A.R.n()) return;
-  uint32_t b = A.R.brick(i);
-  const BrickMeta M = A.T.meta[b];
-  V c, k0, k1, k2;
-  load_cell(A, b, m, c, k0, k1, k2);
-  V u = A.U[b * 64u + m];
-  V rhs = A.B[b * 64u + m];
-  V S = neighbour_sum(A.T, A.cf, A.U, M, m, u, k0, k1, k2);
+  const LaneC<V, CL> L = lane_consts<V, CL>();
+  const LevelView<V, CL, CI> X = level_view(A);
+  const WaveLoop W = wave_loop(A.R.n_leaf);
+  for (uint32_t i = W.first; i < W.end; i += W.step) {
+    uint32_t b = A.R.leaf_lo + i;
+    const BrickMeta M = load_meta(X.meta, b);
+    bool act = (act_mask(M) >> L.m) & 1ull;
+    V c = own_coef<false>(X, b, 0, L.m);
+    V rhs = bload<V>(X.b, L.m, b * 64u);
+    bstore<V>(X.u, L.m, b * 64u, act && L.colour == colour ? div_by(rhs, c) : V(0));
+  }
+}
+
+// Residual, restriction and FAS initial guess from one brick of level l to
+// its parent cells:  b_P = beta_mg (1/alpha) sum_children r,
+// u_P = u*_P = mean of the active children (k_fas_rhs then adds
+// A^{l-1} u* on inner cells).
+template <bool INNER, class V, class CL, class CI>
+__device__ __forceinline__ void restrict_brick(const LevelView<V, CL, CI> &X, const LaneC<V, CL> &L,
+                                               uint32_t b, V scale) {
+  const BrickMeta M = load_meta(X.meta, b);
+  V c = own_coef<INNER>(X, b, 0, L.m);
+  V k0 = own_coef<INNER>(X, b, 1, L.m);
+  V k1 = own_coef<INNER>(X, b, 2, L.m);
+  V k2 = own_coef<INNER>(X, b, 3, L.m);
+  V u = bload<V>(X.u, L.m, b * 64u);
+  V rhs = bload<V>(X.b, L.m, b * 64u);
+  V S = stencil_sum(X, L, b, M, u, k0, k1, k2);
   uint64_t amask = act_mask(M);
-  bool act = (amask >> m) & 1ull;
+  bool act = (amask >> L.m) & 1ull;
   V r = act ? rhs - (c * u - S) : V(0);
   V rs = group8_sum(r);
   V us = group8_sum(act ? u : V(0));
-  int cnt = __popcll((amask >> (m & 56)) & 0xffull);
-  if ((m & 7) == 0) {
-    uint32_t P = uint32_t(M.parent);
-    int q = (octant_of(M) << 3) | (m >> 3);
-    V ust = cnt ? us / V(cnt) : V(0);
-    A.B[P * 64u + q] = rs * scale;
-    A.U[P * 64u + q] = ust;
-    A.Ustar[(P - A.T.nlb) * 64u + q] = ust;
+  int cnt = __popcll((amask >> (L.m & 56u)) & 0xffull);
+  if ((L.m & 7u) == 0) {
+    uint32_t base = uint32_t(M.parent) * 64u + uint32_t(octant_of(M)) * 8u;
+    uint32_t q = L.m >> 3;
+    V ust = cnt ? div_by(us, V(cnt)) : V(0);
+    bstore<V>(X.b, q, base, rs * scale);
+    bstore<V>(X.u, q, base, ust);
+    bstore<V>(X.us, q, base - X.nlb * 64u, ust);
+  }
+}
+
+template <class V, class CL, class CI>
+__global__ void __launch_bounds__(kBlock) k_restrict(LevelArgs<V, CL, CI> A, V scale) {
+  if (A.done && *A.done) return;
+  const LaneC<V, CL> L = lane_consts<V, CL>();
+  const LevelView<V, CL, CI> X = level_view(A);
+  const WaveLoop W = wave_loop(A.R.n());
+  for (uint32_t i = W.first; i < W.end; i += W.step) {
+    if (i < A.R.n_leaf) restrict_brick<false>(X, L, A.R.leaf_lo + i, scale);
+    else restrict_brick<true>(X, L, A.R.inner_lo + (i - A.R.n_leaf), scale);
   }
 }
 
@@ -394,34 +573,40 @@ __global__ void __launch_bounds__(kBlock) k_restrict(LevelArgs<V, CL, CI> A, V s
 template <class V, class CL, class CI>
 __global__ void __launch_bounds__(kBlock) k_fas_rhs(LevelArgs<V, CL, CI> A) {
   if (A.done && *A.done) return;
-  uint32_t i = blockIdx.x * kWavesPerBlock + wave_id();
-  int m = threadIdx.x & (kWave - 1);
-  if (i >= A.R.n()) return;
-  uint32_t b = A.R.brick(i);
-  const BrickMeta M = A.T.meta[b];
-  V c, k0, k1, k2;
-  load_cell(A, b, m, c, k0, k1, k2);
-  V u = A.U[b * 64u + m];
-  V S = neighbour_sum(A.T, A.cf, A.U, M, m, u, k0, k1, k2);
-  bool act = (act_mask(M) >> m) & 1ull;
-  V rhs = A.B[b * 64u + m];
-  A.B[b * 64u + m] = act ? rhs + (c * u - S) : V(0);
+  const LaneC<V, CL> L = lane_consts<V, CL>();
+  const LevelView<V, CL, CI> X = level_view(A);
+  const WaveLoop W = wave_loop(A.R.n_inner);
+  for (uint32_t i = W.first; i < W.end; i += W.step) {
+    uint32_t b = A.R.inner_lo + i;
+    const BrickMeta M = load_meta(X.meta, b);
+    V c = own_coef<true>(X, b, 0, L.m);
+    V k0 = own_coef<true>(X, b, 1, L.m);
+    V k1 = own_coef<true>(X, b, 2, L.m);
+    V k2 = own_coef<true>(X, b, 3, L.m);
+    V u = bload<V>(X.u, L.m, b * 64u);
+    V rhs = bload<V>(X.b, L.m, b * 64u);
+    V S = stencil_sum(X, L, b, M, u, k0, k1, k2);
+    bool act = (act_mask(M) >> L.m) & 1ull;
+    bstore<V>(X.b, L.m, b * 64u, act ? rhs + (c * u - S) : V(0));
+  }
 }
 
 // Prolongation of the FAS correction: u += u_P - u*_P on active cells.
 template <class V, class CL, class CI>
 __global__ void __launch_bounds__(kBlock) k_prolong(LevelArgs<V, CL, CI> A) {
   if (A.done && *A.done) return;
-  uint32_t i = blockIdx.x * kWavesPerBlock + wave_id();
-  int m = threadIdx.x & (kWave - 1);
-  if (i >= A.R.n()) return;
-  uint32_t b = A.R.brick(i);
-  const BrickMeta M = A.T.meta[b];
-  if (!((act_mask(M) >> m) & 1ull)) return;
-  uint32_t P = uint32_t(M.parent);
-  int q = (octant_of(M) << 3) | (m >> 3);
-  V corr = A.U[P * 64u + q] - A.Ustar[(P - A.T.nlb) * 64u + q];
-  A.U[b * 64u + m] += corr;
+  const LaneC<V, CL> L = lane_consts<V, CL>();
+  const LevelView<V, CL, CI> X = level_view(A);
+  const WaveLoop W = wave_loop(A.R.n());
+  for (uint32_t i = W.first; i < W.end; i += W.step) {
+    uint32_t b = A.R.brick(i);
+    const BrickMeta M = load_meta(X.meta, b);
+    uint32_t base = uint32_t(M.parent) * 64u + uint32_t(octant_of(M)) * 8u;
+    uint32_t q = L.m >> 3;
+    V corr = bload<V>(X.u, q, base) - bload<V>(X.us, q, base - X.nlb * 64u);
+    V u = bload<V>(X.u, L.m, b * 64u);
+    if ((act_mask(M) >> L.m) & 1ull) bstore<V>(X.u, L.m, b * 64u, u + corr);
+  }
 }
 
 // Coarsest level: nu RBGS iterations in one workgroup, (R,B) for the first
@@ -429,24 +614,17 @@ __global__ void __launch_bounds__(kBlock) k_prolong(LevelArgs<V, CL, CI> A) {
 template <class V, class CL, class CI>
 __global__ void __launch_bounds__(1024) k_coarsest(LevelArgs<V, CL, CI> A, int nu) {
   if (A.done && *A.done) return;
+  const LaneC<V, CL> L = lane_consts<V, CL>();
+  const LevelView<V, CL, CI> X = level_view(A);
   uint32_t w = wave_id();
   uint32_t nw = blockDim.x / kWave;
-  int m = threadIdx.x & (kWave - 1);
   int half = nu / 2;
   for (int it = 0; it < nu; ++it) {
     for (int h2 = 0; h2 < 2; ++h2) {
       int colour = it < half ? h2 : 1 - h2;
       for (uint32_t i = w; i < A.R.n(); i += nw) {
-        uint32_t b = A.R.brick(i);
-        const BrickMeta M = A.T.meta[b];
-        V c, k0, k1, k2;
-        load_cell(A, b, m, c, k0, k1, k2);
-        V u = A.U[b * 64u + m];
-        V rhs = A.B[b * 64u + m];
-        V S = neighbour_sum(A.T, A.cf, A.U, M, m, u, k0, k1, k2);
-        bool act = (act_mask(M) >> m) & 1ull;
-        int col = (dev_cx(m) + dev_cy(m) + dev_cz(m)) & 1;
-        if (act && col == colour) A.U[b * 64u + m] = div_by(rhs + S, c);
+        if (i < A.R.n_leaf) smooth_brick<false>(X, L, A.R.leaf_lo + i, colour);
+        else smooth_brick<true>(X, L, A.R.inner_lo + (i - A.R.n_leaf), colour);
       }
       __threadfence_block();
       __syncthreads();

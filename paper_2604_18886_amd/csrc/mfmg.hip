@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -72,6 +73,24 @@ inline unsigned grid_for(int64_t bricks) {
   int64_t g = (bricks + kWavesPerBlock - 1) / kWavesPerBlock;
   return unsigned(g > 0 ? g : 1);
 }
+// Grid of the level kernels (wave_loop): a multiple of 8 workgroups, at
+// most kMaxWavesPerXcd waves per XCD, each looping over its share of bricks.
+// The cap can be changed with the environment variable MFMG_WAVES_PER_XCD
+// (read once), for tuning.
+constexpr int64_t kMaxWavesPerXcd = 1024;
+inline int64_t waves_per_xcd() {
+  static const int64_t v = [] {
+    const char *e = std::getenv("MFMG_WAVES_PER_XCD");
+    long long x = e ? std::atoll(e) : 0;
+    return x > 0 ? int64_t(x) : kMaxWavesPerXcd;
+  }();
+  return v;
+}
+inline unsigned level_grid(int64_t bricks) {
+  int64_t chunk = (bricks + 7) / 8;
+  int64_t waves = std::min<int64_t>(std::max<int64_t>(chunk, 1), waves_per_xcd());
+  return unsigned(8 * ((waves + kWavesPerBlock - 1) / kWavesPerBlock));
+}
 inline unsigned grid_elems(int64_t n, int t) { return unsigned(std::max<int64_t>(1, (n + t - 1) / t)); }
 
 // grid of the Krylov kernels (grid-stride over leaf bricks, one partial sum
@@ -101,8 +120,6 @@ struct DeviceTopology {
   DevBuf<int64_t> fbase;              // per device leaf cell
   DevBuf<uint8_t> fmask;              // per device leaf cell
   DevBuf<int32_t> canon;              // device leaf brick -> canonical leaf brick
-  DevBuf<int32_t> tbricks;            // device leaf bricks with a T-face
-  uint32_t n_tbricks = 0;
   std::vector<Range> range;           // per level
   uint32_t nlb = 0, nb = 0;
 };
@@ -125,6 +142,8 @@ struct mfmg_hierarchy {
   DevBuf<float> coef32;    // nlb * 256 (mixed)
   DevBuf<__half> coef16;   // (nb - nlb) * 256 (mixed)
   DevBuf<float> tc32;      // mixed
+  DevBuf<double> pf64;     // plus-face coefficients, nb * 48 (FP64 cycle, composite operator)
+  DevBuf<float> pf32;      // plus-face coefficients, nb * 48 (mixed cycle)
   double n_active = 0;     // active leaf cells
   // work vectors (device order)
   DevBuf<double> U64, B64, S64;  // FP64 cycle: nb*64, nb*64, (nb-nlb)*64
@@ -305,12 +324,6 @@ static void build_device_topology(const Topology &T, DeviceTopology &D, hipStrea
       fbase[int64_t(D.perm[b]) * kCells + m] = T.cell_fbase[b * kCells + m];
       fmask[int64_t(D.perm[b]) * kCells + m] = T.cell_fmask[b * kCells + m];
     }
-  std::vector<int32_t> tb;
-  for (int64_t b = 0; b < nlb; ++b)
-    if (D.meta_host[b].flags & kFlagT) tb.push_back(int32_t(b));
-  D.n_tbricks = uint32_t(tb.size());
-  if (tb.empty()) tb.push_back(0);
-  D.tbricks.upload(tb, s);
   D.meta.upload(D.meta_host, s);
   D.child.upload(child, s);
   D.fbase.upload(fbase, s);
@@ -414,6 +427,18 @@ extern "C" mfmg_status mfmg_build_hierarchy(const mfmg_coeffs *co, const mfmg_mg
     return fail(MFMG_ERR_INVALID_ARG, "bad precision");
   int64_t nlc = (int64_t(1) << prm->coarsest_level) / kBrick;
   if (nlc * nlc * nlc > 64) return fail(MFMG_ERR_INVALID_ARG, "coarsest level too large");
+  {
+    // the level kernels address their arrays with 32-bit byte offsets
+    const DeviceTopology &D = *co->dt;
+    uint64_t nb = D.nb, nlb = D.nlb, big;
+    if (prm->precision == MFMG_FP64)
+      big = nb * 256 * sizeof(double);
+    else
+      big = std::max(nlb * 256 * sizeof(float), (nb - nlb) * 256 * sizeof(__half));
+    uint64_t ubytes = nb * 64 * (prm->precision == MFMG_FP64 ? sizeof(double) : sizeof(float));
+    if (big > kMaxBufferBytes || ubytes >= kOutOfRange)
+      return fail(MFMG_ERR_INVALID_ARG, "level arrays exceed the 32-bit offset range");
+  }
   hipStream_t s = (hipStream_t)stream;
   try {
     std::unique_ptr<mfmg_hierarchy> h(new mfmg_hierarchy());
@@ -441,6 +466,9 @@ extern "C" mfmg_status mfmg_build_hierarchy(const mfmg_coeffs *co, const mfmg_mg
                          (const double *)h->coef64.p, R.inner_lo, R.n_inner, h->meta.p);
     }
     HIP_CHECK(hipGetLastError());
+    h->pf64.alloc(size_t(nb) * 48);
+    hipLaunchKernelGGL(k_plus_faces<double>, dim3(grid_for(nb)), dim3(kBlock), 0, s, topo,
+                       (const double *)h->coef64.p, (const double *)co->tc.p, h->pf64.p, 0);
     if (prm->precision == MFMG_MIXED) {
       h->coef32.alloc(size_t(nlb) * 256);
       h->coef16.alloc(size_t(nb - nlb) * 256 + 1);
@@ -452,6 +480,9 @@ extern "C" mfmg_status mfmg_build_hierarchy(const mfmg_coeffs *co, const mfmg_mg
       if (nb > nlb)
         hipLaunchKernelGGL(k_convert_inner, dim3(grid_for(nb - nlb)), dim3(kBlock), 0, s,
                            (const double *)h->coef64.p, topo, h->coef16.p);
+      h->pf32.alloc(size_t(nb) * 48);
+      hipLaunchKernelGGL(k_plus_faces<float>, dim3(grid_for(nb)), dim3(kBlock), 0, s, topo,
+                         (const double *)h->coef64.p, (const double *)co->tc.p, h->pf32.p, 1);
       h->U32.alloc(size_t(nb) * 64);
       h->B32.alloc(size_t(nb) * 64);
       h->S32.alloc(size_t(nb - nlb) * 64 + 1);
@@ -465,7 +496,8 @@ extern "C" mfmg_status mfmg_build_hierarchy(const mfmg_coeffs *co, const mfmg_mg
     h->pd.alloc(size_t(nb) * 64);
     h->Xf.alloc(size_t(nb) * 64);
     h->Ap.alloc(size_t(N));
-    h->partials.alloc(std::max<int64_t>(kMaxReduceBlocks, grid_for(nlb)));
+    h->partials.alloc(std::max<int64_t>({kMaxReduceBlocks, int64_t(grid_for(nlb)) + 8,
+                                         int64_t(level_grid(nlb))}));
     h->S.alloc(1);
     HIP_CHECK(hipMemsetAsync(h->S.p, 0, sizeof(Scalars), s));
     HIP_CHECK(hipHostMalloc(&h->hostS, sizeof(Scalars), hipHostMallocDefault));
@@ -535,7 +567,7 @@ struct Cycle {
   const mfmg_hierarchy *h;
   const CL *leafc;
   const CI *innerc;
-  const CL *tc;
+  const CL *pf;
   V *U, *B, *Ust;
   const int *done;
   hipStream_t s;
@@ -549,9 +581,10 @@ struct Cycle {
     A.T = make_topo(D, h->meta.p);
     A.cf.leaf = leafc;
     A.cf.inner = innerc;
-    A.cf.tc = tc;
+    A.cf.tc = nullptr;
     A.cf.nlb = D.nlb;
     A.cf.iscale = iscale(l);
+    A.pf = pf;
     A.U = U;
     A.B = B;
     A.Ustar = Ust;
@@ -564,16 +597,28 @@ struct Cycle {
     return A;
   }
 
-  void smooth(int l, int first, int nu) const {
+  void half_sweep(const LevelArgs<V, CL, CI> &A, int colour) const {
+    hipLaunchKernelGGL((k_smooth<V, CL, CI>), dim3(level_grid(A.R.n())), dim3(kBlock), 0, s, A,
+                       colour);
+  }
+  void smooth(int l, int first, int nu, bool zero_start = false) const {
     auto A = args(l, false);
     if (A.R.n() == 0) return;
     for (int it = 0; it < nu; ++it)
-      for (int c = 0; c < 2; ++c)
-        hipLaunchKernelGGL((k_smooth<V, CL, CI>), dim3(grid_for(A.R.n())), dim3(kBlock), 0, s,
-                           A, c == 0 ? first : 1 - first);
+      for (int c = 0; c < 2; ++c) {
+        int colour = c == 0 ? first : 1 - first;
+        if (zero_start && it == 0 && c == 0)
+          hipLaunchKernelGGL((k_smooth_zero<V, CL, CI>), dim3(level_grid(A.R.n())),
+                             dim3(kBlock), 0, s, A, colour);
+        else
+          half_sweep(A, colour);
+      }
   }
 
-  void fas(int l) const {
+  // zero_start: the level's iterate is zero and its bricks are all leaves
+  // (the finest level at the start of a cycle), so the first half-sweep
+  // needs no neighbour values and also clears the iterate.
+  void fas(int l, bool zero_start = false) const {
     const mfmg_mg_params &p = h->prm;
     if (l == h->lc) {
       auto A = args(l, false);
@@ -582,36 +627,42 @@ struct Cycle {
                          p.nu_coarse);
       return;
     }
-    smooth(l, 0, p.nu_pre);
+    smooth(l, 0, p.nu_pre, zero_start);
     auto A = args(l, false);
     V scale = V(p.beta_mg / p.alpha);
-    hipLaunchKernelGGL((k_restrict<V, CL, CI>), dim3(grid_for(A.R.n())), dim3(kBlock), 0, s, A,
-                       scale);
+    hipLaunchKernelGGL((k_restrict<V, CL, CI>), dim3(level_grid(A.R.n())), dim3(kBlock), 0, s,
+                       A, scale);
     auto C = args(l - 1, true);
     if (C.R.n())
-      hipLaunchKernelGGL((k_fas_rhs<V, CL, CI>), dim3(grid_for(C.R.n())), dim3(kBlock), 0, s,
-                         C);
+      hipLaunchKernelGGL((k_fas_rhs<V, CL, CI>), dim3(level_grid(C.R.n_inner)), dim3(kBlock), 0,
+                         s, C);
     for (int k = 0; k < p.mu; ++k) fas(l - 1);
-    hipLaunchKernelGGL((k_prolong<V, CL, CI>), dim3(grid_for(A.R.n())), dim3(kBlock), 0, s, A);
+    hipLaunchKernelGGL((k_prolong<V, CL, CI>), dim3(level_grid(A.R.n())), dim3(kBlock), 0, s,
+                       A);
     smooth(l, 1, p.nu_post);
   }
 
   void run() const {
-    int64_t N = int64_t(h->co->dt->nlb) * 64;
-    hipLaunchKernelGGL((k_fill<V>), dim3(grid_elems(N, 256)), dim3(256), 0, s, U, N, V(0));
-    fas(h->L);
+    const Range &RL = h->co->dt->range[h->L];
+    bool zero_start = h->L > h->lc && h->prm.nu_pre > 0 && RL.n_inner == 0 && RL.leaf_lo == 0;
+    int64_t lo = zero_start ? int64_t(RL.n_leaf) * 64 : 0;
+    int64_t N = int64_t(h->co->dt->nlb) * 64 - lo;
+    if (N > 0)
+      hipLaunchKernelGGL((k_fill<V>), dim3(grid_elems(N, 256)), dim3(256), 0, s, U + lo, N,
+                         V(0));
+    fas(h->L, zero_start);
   }
 };
 
 void run_cycle(const mfmg_hierarchy *h, hipStream_t s, const int *done) {
   if (h->prm.precision == MFMG_MIXED) {
-    Cycle<float, float, __half> c{h, h->coef32.p, h->coef16.p, h->tc32.p,
+    Cycle<float, float, __half> c{h, h->coef32.p, h->coef16.p, h->pf32.p,
                                   h->U32.p, h->B32.p, h->S32.p, done, s};
     c.run();
   } else {
     // FP64 inner coefficients directly follow the leaf ones in coef64
     Cycle<double, double, double> c{h, h->coef64.p, h->coef64.p + int64_t(h->co->dt->nlb) * 256,
-                                    h->co->tc.p, h->U64.p, h->B64.p, h->S64.p, done, s};
+                                    h->pf64.p, h->U64.p, h->B64.p, h->S64.p, done, s};
     c.run();
   }
 }
@@ -738,6 +789,7 @@ PcgArgs pcg_args(mfmg_hierarchy *h) {
   P.T = make_topo(*h->co->dt, h->meta.p);
   P.C = h->coef64.p;
   P.TC = h->co->tc.p;
+  P.PF = h->pf64.p;
   P.canon = h->co->dt->canon.p;
   P.S = h->S.p;
   P.partials = h->partials.p;
@@ -759,10 +811,10 @@ extern "C" mfmg_status mfmg_apply_operator(mfmg_hierarchy *h, const double *x, d
     PcgArgs P = pcg_args(h);
     hipLaunchKernelGGL(k_full, dim3(G), dim3(kBlock), 0, s, P, x, h->Xf.p, 1);
     if (transpose)
-      hipLaunchKernelGGL(k_apply<true>, dim3(G), dim3(kBlock), 0, s, P, (const double *)h->Xf.p,
+      hipLaunchKernelGGL(k_applyT, dim3(G), dim3(kBlock), 0, s, P, (const double *)h->Xf.p,
                          h->Ap.p);
     else
-      hipLaunchKernelGGL(k_apply<false>, dim3(G), dim3(kBlock), 0, s, P,
+      hipLaunchKernelGGL(k_apply, dim3(level_grid(h->co->dt->nlb)), dim3(kBlock), 0, s, P,
                          (const double *)h->Xf.p, h->Ap.p);
     hipLaunchKernelGGL(k_to_canonical<double>, dim3(G), dim3(kBlock), 0, s, P,
                        (const double *)h->Ap.p, y);
@@ -813,6 +865,39 @@ extern "C" mfmg_status mfmg_apply_precond(mfmg_hierarchy *h, const double *r, do
 // --------------------------------------------------------------------------
 // PCG (Algorithm 1)
 // --------------------------------------------------------------------------
+// Reductions of the PCG: the kernel stores one partial per workgroup and
+// k_finish adds them in fixed order and updates the scalars.
+struct Reduce {
+  PcgArgs P;
+  hipStream_t s;
+  unsigned G;  // grid of the flat leaf kernels
+
+  Reduce(mfmg_hierarchy *h, hipStream_t s_) : P(pcg_args(h)), s(s_) {
+    G = grid_reduce(h->co->dt->nlb);
+  }
+  void finish(unsigned n, int op, int arg = 0, double rtol = 0.0) const {
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, P, int64_t(n), op, arg, rtol);
+  }
+  template <class V>
+  void init(const double *rhs, double *r, V *r_low, double *x, double rtol) const {
+    hipLaunchKernelGGL(k_pcg_init<V>, dim3(G), dim3(kBlock), 0, s, P, rhs, r, r_low, x);
+    finish(G, kFinInit, 0, rtol);
+  }
+  // v -= mean over active cells (Section 2.2); mode as k_shift_mean
+  template <class V>
+  void shift_mean(double *v, V *v_low, double na, int mode, double rtol) const {
+    hipLaunchKernelGGL(k_sum_active, dim3(G), dim3(kBlock), 0, s, P, (const double *)v);
+    finish(G, kFinSum);
+    hipLaunchKernelGGL(k_shift_mean<V>, dim3(G), dim3(kBlock), 0, s, P, v, v_low, na, mode);
+    if (mode != 3) finish(G, kFinShift, mode, rtol);
+  }
+  void true_resid(const double *rhs, const double *X, uint32_t nlb) const {
+    unsigned g = level_grid(nlb);
+    hipLaunchKernelGGL(k_true_resid, dim3(g), dim3(kBlock), 0, s, P, rhs, X);
+    finish(g, kFinTrue);
+  }
+};
+
 // Launch helpers of one Krylov iteration (Algorithm 1).
 template <class V>
 struct Krylov {
@@ -820,37 +905,41 @@ struct Krylov {
   PcgArgs P;
   hipStream_t s;
   unsigned G;   // grid of the flat vector kernels
-  unsigned GB;  // one wave per leaf brick
+  unsigned GB;  // one wave per leaf brick (transposed operator)
+  unsigned GA;  // wave_loop grid of the forward operator
   int64_t n2;   // leaf entries / 2
 
   Krylov(mfmg_hierarchy *h_, hipStream_t s_) : h(h_), s(s_) {
     P = pcg_args(h);
     G = grid_reduce(h->co->dt->nlb);
     GB = grid_for(h->co->dt->nlb);
+    GA = level_grid(h->co->dt->nlb);
     n2 = int64_t(h->co->dt->nlb) * 32;
   }
   void rz(const double *r, const V *z, int first) const {
-    hipLaunchKernelGGL(k_pcg_rz<V>, dim3(G), dim3(kBlock), 0, s, P, r, z, first, n2);
+    hipLaunchKernelGGL(k_pcg_rz<V>, dim3(G), dim3(kBlock), 0, s, P, r, z, n2);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, P, int64_t(G), int(kFinRz), first,
+                       0.0);
   }
   void pupdate(const V *z, int first) const {
-    hipLaunchKernelGGL(k_pcg_p<V>, dim3(G), dim3(kBlock), 0, s, P, z, h->pd.p, first, n2);
-    const DeviceTopology &D = *h->co->dt;
-    if (D.n_tbricks)
-      hipLaunchKernelGGL(k_average_up, dim3(grid_for(D.n_tbricks)), dim3(kBlock), 0, s, P,
-                         (const int32_t *)D.tbricks.p, D.n_tbricks, h->pd.p);
+    hipLaunchKernelGGL(k_pcg_p<V>, dim3(GA), dim3(kBlock), 0, s, P, z, h->pd.p, first);
   }
   void Ap(bool trans) const {
     if (trans)
-      hipLaunchKernelGGL(k_pcg_Ap<true>, dim3(GB), dim3(kBlock), 0, s, P,
-                         (const double *)h->pd.p, h->Ap.p);
+      hipLaunchKernelGGL(k_pcg_ApT, dim3(GB), dim3(kBlock), 0, s, P, (const double *)h->pd.p,
+                         h->Ap.p);
     else
-      hipLaunchKernelGGL(k_pcg_Ap<false>, dim3(GB), dim3(kBlock), 0, s, P,
-                         (const double *)h->pd.p, h->Ap.p);
-    hipLaunchKernelGGL(k_finish_alpha, dim3(1), dim3(1024), 0, s, P, int64_t(GB));
+      hipLaunchKernelGGL(k_pcg_Ap, dim3(GA), dim3(kBlock), 0, s, P, (const double *)h->pd.p,
+                         h->Ap.p);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, P, int64_t(trans ? GB : GA),
+                       int(kFinAlpha), 0, 0.0);
   }
   void update(double *x, double *r, V *r_low, int defer) const {
     hipLaunchKernelGGL(k_pcg_update<V>, dim3(G), dim3(kBlock), 0, s, P, x, r, r_low,
                        (const double *)h->pd.p, (const double *)h->Ap.p, defer, n2);
+    if (!defer)
+      hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, P, int64_t(G), int(kFinUpdate),
+                         0, 0.0);
   }
 };
 
@@ -859,15 +948,12 @@ static void pcg_iterate(mfmg_hierarchy *h, const double *rhs, double *r, V *r_lo
                         const mfmg_solve_params *sp, bool null_space, hipStream_t s) {
   PcgArgs P = pcg_args(h);
   unsigned G = grid_reduce(h->co->dt->nlb);
+  Reduce R(h, s);
   const int *done = &h->S.p->done;
   double na = std::max(1.0, h->n_active);
   double *x = h->x.p;
-  hipLaunchKernelGGL(k_pcg_init<V>, dim3(G), dim3(kBlock), 0, s, P, rhs, r, r_low, x, sp->rtol);
-  if (null_space) {
-    hipLaunchKernelGGL(k_sum_active, dim3(G), dim3(kBlock), 0, s, P, (const double *)r);
-    hipLaunchKernelGGL(k_shift_mean<V>, dim3(G), dim3(kBlock), 0, s, P, r, r_low, na, 0,
-                       sp->rtol);
-  }
+  R.init<V>(rhs, r, r_low, x, sp->rtol);
+  if (null_space) R.shift_mean<V>(r, r_low, na, 0, sp->rtol);
   Krylov<V> K(h, s);
   run_cycle(h, s, done);
   K.rz(r, z, 1);
@@ -875,11 +961,7 @@ static void pcg_iterate(mfmg_hierarchy *h, const double *rhs, double *r, V *r_lo
   for (int it = 0; it < sp->max_iter; ++it) {
     K.Ap(false);
     K.update(x, r, r_low, int(null_space));
-    if (null_space) {
-      hipLaunchKernelGGL(k_sum_active, dim3(G), dim3(kBlock), 0, s, P, (const double *)r);
-      hipLaunchKernelGGL(k_shift_mean<V>, dim3(G), dim3(kBlock), 0, s, P, r, r_low, na, 1,
-                         sp->rtol);
-    }
+    if (null_space) R.shift_mean<V>(r, r_low, na, 1, sp->rtol);
     run_cycle(h, s, done);
     K.rz(r, z, 0);
     K.pupdate(z, 0);
@@ -887,22 +969,15 @@ static void pcg_iterate(mfmg_hierarchy *h, const double *rhs, double *r, V *r_lo
     HIP_CHECK(hipStreamSynchronize(s));
     if (h->hostS->done) break;
   }
-  if (null_space) {
-    // zero-mean solution, then the true residual shifted to zero mean
-    hipLaunchKernelGGL(k_sum_active, dim3(G), dim3(kBlock), 0, s, P, (const double *)x);
-    hipLaunchKernelGGL(k_shift_mean<double>, dim3(G), dim3(kBlock), 0, s, P, x,
-                       (double *)nullptr, na, 3, 0.0);
-  }
+  // zero-mean solution, then the true residual shifted to zero mean
+  if (null_space) R.shift_mean<double>(x, (double *)nullptr, na, 3, 0.0);
   hipLaunchKernelGGL(k_full, dim3(G), dim3(kBlock), 0, s, P, (const double *)x, h->Xf.p, 0);
   if (null_space) {
-    hipLaunchKernelGGL(k_residual_vec, dim3(G), dim3(kBlock), 0, s, P, rhs,
-                       (const double *)h->Xf.p, h->Ap.p);
-    hipLaunchKernelGGL(k_sum_active, dim3(G), dim3(kBlock), 0, s, P, (const double *)h->Ap.p);
-    hipLaunchKernelGGL(k_shift_mean<double>, dim3(G), dim3(kBlock), 0, s, P, h->Ap.p,
-                       (double *)nullptr, na, 2, 0.0);
+    hipLaunchKernelGGL(k_residual_vec, dim3(level_grid(h->co->dt->nlb)), dim3(kBlock), 0, s,
+                       P, rhs, (const double *)h->Xf.p, h->Ap.p);
+    R.shift_mean<double>(h->Ap.p, (double *)nullptr, na, 2, 0.0);
   } else {
-    hipLaunchKernelGGL(k_true_resid, dim3(G), dim3(kBlock), 0, s, P, rhs,
-                       (const double *)h->Xf.p);
+    R.true_resid(rhs, (const double *)h->Xf.p, h->co->dt->nlb);
   }
   HIP_CHECK(hipGetLastError());
 }
@@ -967,15 +1042,11 @@ static void pcg_adjoint_iterate(mfmg_hierarchy *h, const double *g, V *z,
                                 const mfmg_solve_params *sp, bool null_space, hipStream_t s) {
   PcgArgs P = pcg_args(h);
   unsigned G = grid_reduce(h->co->dt->nlb);
+  Reduce R(h, s);
   double na = std::max(1.0, h->n_active);
   double *x = h->x.p, *r = h->rA.p;
-  hipLaunchKernelGGL(k_pcg_init<V>, dim3(G), dim3(kBlock), 0, s, P, g, r, (V *)nullptr, x,
-                     sp->rtol);
-  if (null_space) {
-    hipLaunchKernelGGL(k_sum_active, dim3(G), dim3(kBlock), 0, s, P, (const double *)r);
-    hipLaunchKernelGGL(k_shift_mean<V>, dim3(G), dim3(kBlock), 0, s, P, r, (V *)nullptr, na, 0,
-                       sp->rtol);
-  }
+  R.init<V>(g, r, (V *)nullptr, x, sp->rtol);
+  if (null_space) R.shift_mean<V>(r, (V *)nullptr, na, 0, sp->rtol);
   HIP_CHECK(hipMemcpyAsync(h->hostS, h->S.p, sizeof(Scalars), hipMemcpyDeviceToHost, s));
   HIP_CHECK(hipStreamSynchronize(s));
   if (!h->hostS->done) {
@@ -986,11 +1057,7 @@ static void pcg_adjoint_iterate(mfmg_hierarchy *h, const double *g, V *z,
     for (int it = 0; it < sp->max_iter; ++it) {
       K.Ap(true);
       K.update(x, r, (V *)nullptr, int(null_space));
-      if (null_space) {
-        hipLaunchKernelGGL(k_sum_active, dim3(G), dim3(kBlock), 0, s, P, (const double *)r);
-        hipLaunchKernelGGL(k_shift_mean<V>, dim3(G), dim3(kBlock), 0, s, P, r, (V *)nullptr, na,
-                           1, sp->rtol);
-      }
+      if (null_space) R.shift_mean<V>(r, (V *)nullptr, na, 1, sp->rtol);
       HIP_CHECK(hipMemcpyAsync(h->hostS, h->S.p, sizeof(Scalars), hipMemcpyDeviceToHost, s));
       HIP_CHECK(hipStreamSynchronize(s));
       if (h->hostS->done) break;
@@ -999,14 +1066,10 @@ static void pcg_adjoint_iterate(mfmg_hierarchy *h, const double *g, V *z,
       K.pupdate(z, 0);
     }
   }
-  if (null_space) {
-    hipLaunchKernelGGL(k_sum_active, dim3(G), dim3(kBlock), 0, s, P, (const double *)x);
-    hipLaunchKernelGGL(k_shift_mean<double>, dim3(G), dim3(kBlock), 0, s, P, x,
-                       (double *)nullptr, na, 3, 0.0);
-  }
+  if (null_space) R.shift_mean<double>(x, (double *)nullptr, na, 3, 0.0);
   // true residual ||g - A^T lambda||
   hipLaunchKernelGGL(k_full, dim3(G), dim3(kBlock), 0, s, P, (const double *)x, h->Xf.p, 0);
-  hipLaunchKernelGGL(k_apply<true>, dim3(G), dim3(kBlock), 0, s, P, (const double *)h->Xf.p,
+  hipLaunchKernelGGL(k_applyT, dim3(G), dim3(kBlock), 0, s, P, (const double *)h->Xf.p,
                      h->Ap.p);
   HIP_CHECK(hipGetLastError());
 }
@@ -1202,19 +1265,15 @@ extern "C" mfmg_status mfmg_profile(mfmg_hierarchy *h, int what, int level, int 
     auto launch = [&]() {
       if (what == MFMG_PROFILE_SMOOTH) {
         if (mixed) {
-          Cycle<float, float, __half> c{h, h->coef32.p, h->coef16.p, h->tc32.p,
+          Cycle<float, float, __half> c{h, h->coef32.p, h->coef16.p, h->pf32.p,
                                         h->U32.p, h->B32.p, h->S32.p, nullptr, s};
-          auto A = c.args(level, false);
-          hipLaunchKernelGGL((k_smooth<float, float, __half>), dim3(grid_for(A.R.n())),
-                             dim3(kBlock), 0, s, A, 0);
+          c.half_sweep(c.args(level, false), 0);
         } else {
           Cycle<double, double, double> c{h, h->coef64.p,
                                           h->coef64.p + int64_t(h->co->dt->nlb) * 256,
-                                          h->co->tc.p, h->U64.p, h->B64.p, h->S64.p,
+                                          h->pf64.p, h->U64.p, h->B64.p, h->S64.p,
                                           nullptr, s};
-          auto A = c.args(level, false);
-          hipLaunchKernelGGL((k_smooth<double, double, double>), dim3(grid_for(A.R.n())),
-                             dim3(kBlock), 0, s, A, 0);
+          c.half_sweep(c.args(level, false), 0);
         }
       } else {
         run_cycle(h, s, nullptr);

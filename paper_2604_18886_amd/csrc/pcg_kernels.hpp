@@ -13,6 +13,7 @@ struct PcgArgs {
   Topo T;
   const double *C;       // FP64 coefficients of all bricks (device order)
   const double *TC;      // FP64 plus-side T-face coefficients
+  const double *PF;      // FP64 plus-face coefficients of all bricks, 48 per brick
   const int32_t *canon;  // device leaf brick -> canonical leaf brick
   Scalars *S;
   double *partials;
@@ -26,61 +27,6 @@ __device__ __forceinline__ void leaf_cell(const PcgArgs &P, uint32_t b, int m, d
   k0 = cf[64 + m];
   k1 = cf[128 + m];
   k2 = cf[192 + m];
-}
-
-// Composite leaf operator, forward.  X and C cover all bricks: where a
-// leaf's same-level neighbour is an inner cell P, X holds the mean of P's
-// active children (written by average_up) and C holds P's Algorithm 3
-// coefficients, whose face coefficient is the sum of the fine sub-face
-// coefficients over 2 -- the coarse side of the T-junction.  The fine side
-// uses the ghost of Eq. (10).
-__device__ __forceinline__ double composite_Au(const Topo &T, const double *__restrict__ C,
-                                               const double *__restrict__ TC,
-                                               const double *__restrict__ X,
-                                               const BrickMeta &M, int m, double u, double c,
-                                               double k0, double k1, double k2) {
-  double v[6], k[6];
-#pragma unroll
-  for (int d = 0; d < 6; ++d) {
-    int a = d >> 1;
-    int p = dev_partner(m, d);
-    double kown = a == 0 ? k0 : (a == 1 ? k1 : k2);
-    v[d] = shfl(u, p);
-    k[d] = (d & 1) ? shfl(kown, p) : kown;
-  }
-#pragma unroll
-  for (int d = 0; d < 6; ++d) {
-    int p = dev_partner(m, d);
-    if (dev_outside(m, d) && M.nbr[d] >= 0) {
-      v[d] = X[uint32_t(M.nbr[d]) * 64u + p];
-      if (d & 1) k[d] = C[uint32_t(M.nbr[d]) * 256u + (1 + (d >> 1)) * 64 + p];
-    }
-  }
-#pragma unroll
-  for (int d = 0; d < 6; ++d)
-    if (dev_outside(m, d) && ((M.flags >> (16 + d)) & 1u)) v[d] = 0.0;
-  uint64_t amask = act_mask(M);
-  bool act = (amask >> m) & 1ull;
-  if (M.flags & kFlagT) {
-    double s = group8_sum(act ? u : 0.0);
-    int cnt = __popcll((amask >> (m & 56)) & 0xffull);
-    double ubar = cnt ? s / double(cnt) : 0.0;
-#pragma unroll
-    for (int d = 0; d < 6; ++d) {
-      if (((M.flags >> d) & 1u) && dev_outside(m, d)) {
-        int32_t J = dev_decode_coarse(M.nbr[d]);
-        const BrickMeta MJ = T.meta[J];
-        double uJ = X[uint32_t(J) * 64u + coarse_local(M, m, d, MJ)];
-        v[d] = u + (uJ - ubar) * 0.5;
-        if (d & 1)
-          k[d] = TC[uint32_t(M.tplus) * 48u + (d >> 1) * 16 + dev_face_index(m, d >> 1)];
-      }
-    }
-  }
-  double acc = c * u;
-#pragma unroll
-  for (int d = 0; d < 6; ++d) acc -= k[d] * v[d];
-  return act ? acc : 0.0;
 }
 
 // Transposed composite operator (adjoint path).  Its T-junction blocks are
@@ -159,6 +105,56 @@ __device__ __forceinline__ void average_up(double *__restrict__ X, const BrickMe
     X[uint32_t(M.parent) * 64u + ((octant_of(M) << 3) | (m >> 3))] = cnt ? s / double(cnt) : 0.0;
 }
 
+// The forward composite operator is the finest-level stencil applied to a
+// full-size vector whose inner cells hold the mean of their active children
+// (average_up): an inner neighbour's plus-face coefficient is its Algorithm 3
+// k, the sum of the fine sub-face coefficients over 2 (the coarse side of a
+// T-junction), and the fine side takes the ghost of Eq. (10).  It therefore
+// runs through stencil_sum, on the FP64 coefficient arrays.
+__device__ __forceinline__ LevelView<double, double, double> composite_view(const PcgArgs &P,
+                                                                            const double *X) {
+  LevelView<double, double, double> V;
+  uint64_t nb = P.T.nb, nlb = P.T.nlb;
+  V.u = make_rsrc(X, nb * 64 * sizeof(double));
+  V.b = V.u;
+  V.us = V.u;
+  V.cl = make_rsrc(P.C, nlb * 256 * sizeof(double));
+  V.ci = make_rsrc(P.C + nlb * 256, (nb - nlb) * 256 * sizeof(double));
+  V.pf = make_rsrc(P.PF, nb * 48 * sizeof(double));
+  V.meta = P.T.meta;
+  V.nlb = P.T.nlb;
+  V.iscale = 1.0;
+  return V;
+}
+
+// y = (A X)_m at the lane's cell of leaf brick b (0 on inactive cells); u = X_m.
+__device__ __forceinline__ double composite_row(const LevelView<double, double, double> &V,
+                                                const LaneC<double, double> &L, uint32_t b,
+                                                double &u) {
+  const BrickMeta M = load_meta(V.meta, b);
+  double c = own_coef<false>(V, b, 0, L.m);
+  double k0 = own_coef<false>(V, b, 1, L.m);
+  double k1 = own_coef<false>(V, b, 2, L.m);
+  double k2 = own_coef<false>(V, b, 3, L.m);
+  u = bload<double>(V.u, L.m, b * 64u);
+  double S = stencil_sum(V, L, b, M, u, k0, k1, k2);
+  bool act = (act_mask(M) >> L.m) & 1ull;
+  return act ? c * u - S : 0.0;
+}
+
+// per-workgroup partial of a wave-private sum, in fixed order
+__device__ __forceinline__ void block_partial(double part, double *partials) {
+  __shared__ double red[kWavesPerBlock];
+  part = wave_sum(part);
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x >> 6] = part;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kWavesPerBlock; ++w) s += red[w];
+    partials[blockIdx.x] = s;
+  }
+}
+
 // grid-stride loop of one wave over the leaf bricks
 #define LEAF_LOOP(P)                                                     \
   int m = threadIdx.x & (kWave - 1);                                     \
@@ -168,7 +164,7 @@ __device__ __forceinline__ void average_up(double *__restrict__ X, const BrickMe
 // r = rhs (canonical order) on active cells, x = 0, ||r||^2
 template <class V>
 __global__ void __launch_bounds__(kBlock) k_pcg_init(PcgArgs P, const double *rhs, double *r,
-                                                     V *r_low, double *x, double rtol) {
+                                                     V *r_low, double *x) {
   double part = 0.0;
   LEAF_LOOP(P) {
     const BrickMeta M = P.T.meta[b];
@@ -179,18 +175,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_init(PcgArgs P, const double *rh
     x[b * 64u + m] = 0.0;
     part += v * v;
   }
-  Scalars *S = P.S;
-  block_reduce_finish(part, P.partials, &S->ticket[0], [&](double tot) {
-    S->rr0 = tot;
-    S->rr = tot;
-    S->tol2 = rtol * rtol * tot;
-    S->iters = 0;
-    S->status = 0;
-    S->done = (tot == 0.0) || !(tot < INFINITY);
-    if (!(tot < INFINITY)) S->status = -5;
-    S->rz = 0.0;
-    P.hist[0] = tot > 0.0 ? 1.0 : 0.0;
-  });
+  block_partial(part, P.partials);
 }
 
 // Flat vector kernels: the leaf vectors of the Krylov iteration are
@@ -210,7 +195,7 @@ struct Vec2<float> {
 // (r, z) and beta = (r, z) / (r, z)_old (beta = 0 on the first call)
 template <class V>
 __global__ void __launch_bounds__(kBlock) k_pcg_rz(PcgArgs P, const double *r, const V *z,
-                                                   int first, int64_t n2) {
+                                                   int64_t n2) {
   if (P.S->done) return;
   double part = 0.0;
   const double2 *r2 = reinterpret_cast<const double2 *>(r);
@@ -221,59 +206,50 @@ __global__ void __launch_bounds__(kBlock) k_pcg_rz(PcgArgs P, const double *r, c
     auto b = z2[i];
     part += a.x * double(b.x) + a.y * double(b.y);
   }
-  Scalars *S = P.S;
-  block_reduce_finish(part, P.partials, &S->ticket[1], [&](double tot) {
-    if (!(tot > 0.0) || !(tot < INFINITY)) {
-      S->status = -5;
-      S->done = 1;
-      return;
-    }
-    S->beta = first ? 0.0 : tot / S->rz;
-    S->rz = tot;
-  });
+  block_partial(part, P.partials);
 }
 
-// p = z + beta p (p = z on the first call)
+// p = z + beta p (p = z on the first call) over the leaf bricks, and for
+// bricks with a T-face the mean of each active sibling group written to the
+// parent's slot of the full-size p: the value the forward composite operator
+// reads for an inner neighbour.
 template <class V>
-__global__ void __launch_bounds__(kBlock) k_pcg_p(PcgArgs P, const V *z, double *p, int first,
-                                                  int64_t n2) {
+__global__ void __launch_bounds__(kBlock) k_pcg_p(PcgArgs P, const V *z, double *p, int first) {
   if (P.S->done) return;
   double beta = first ? 0.0 : P.S->beta;
-  double2 *p2 = reinterpret_cast<double2 *>(p);
-  const typename Vec2<V>::T *z2 = reinterpret_cast<const typename Vec2<V>::T *>(z);
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n2;
-       i += int64_t(gridDim.x) * blockDim.x) {
-    auto b = z2[i];
-    double2 v;
-    if (first) {
-      v.x = double(b.x);
-      v.y = double(b.y);
-    } else {
-      double2 a = p2[i];
-      v.x = double(b.x) + beta * a.x;
-      v.y = double(b.y) + beta * a.y;
-    }
-    p2[i] = v;
+  uint32_t m = threadIdx.x & (kWave - 1);
+  const __amdgpu_buffer_rsrc_t zr = make_rsrc(z, uint64_t(P.T.nlb) * 64 * sizeof(V));
+  const __amdgpu_buffer_rsrc_t pr = make_rsrc(p, uint64_t(P.T.nb) * 64 * sizeof(double));
+  const WaveLoop W = wave_loop(P.T.nlb);
+  for (uint32_t b = W.first; b < W.end; b += W.step) {
+    double v = double(bload<V>(zr, m, b * 64u));
+    if (!first) v += beta * bload<double>(pr, m, b * 64u);
+    bstore<double>(pr, m, b * 64u, v);
+    const BrickMeta M = load_meta(P.T.meta, b);
+    if (M.flags & kFlagT) average_up(p, M, int(m), v);
   }
 }
 
-// Parent means of the leaf bricks with T-faces (list), read by the forward
-// composite operator for inner neighbours.
-__global__ void __launch_bounds__(kBlock) k_average_up(PcgArgs P, const int32_t *list,
-                                                       uint32_t n, double *X) {
-  if (P.S && P.S->done) return;
-  uint32_t i = blockIdx.x * kWavesPerBlock + wave_id();
-  int m = threadIdx.x & (kWave - 1);
-  if (i >= n) return;
-  uint32_t b = uint32_t(list[i]);
-  const BrickMeta M = P.T.meta[b];
-  average_up(X, M, m, X[b * 64u + m]);
+// Ap = A p over the leaf bricks (wave_loop grid); each workgroup stores its
+// partial (p, Ap), k_finish_alpha adds them in fixed order.
+__global__ void __launch_bounds__(kBlock) k_pcg_Ap(PcgArgs P, const double *p, double *Ap) {
+  if (P.S->done) return;
+  const LevelView<double, double, double> V = composite_view(P, p);
+  const LaneC<double, double> L = lane_consts<double, double>();
+  const __amdgpu_buffer_rsrc_t out = make_rsrc(Ap, uint64_t(P.T.nlb) * 64 * sizeof(double));
+  const WaveLoop W = wave_loop(P.T.nlb);
+  double part = 0.0;
+  for (uint32_t b = W.first; b < W.end; b += W.step) {
+    double u;
+    double y = composite_row(V, L, b, u);
+    bstore<double>(out, L.m, b * 64u, y);
+    part += u * y;
+  }
+  block_partial(part, P.partials);
 }
 
-// Ap = A p (TRANS: A^T p, for the adjoint), one wave per leaf brick; each
-// workgroup stores its partial (p, Ap), k_finish_alpha adds them.
-template <bool TRANS>
-__global__ void __launch_bounds__(kBlock) k_pcg_Ap(PcgArgs P, const double *p, double *Ap) {
+// Ap = A^T p (adjoint solves), one wave per leaf brick.
+__global__ void __launch_bounds__(kBlock) k_pcg_ApT(PcgArgs P, const double *p, double *Ap) {
   if (P.S->done) return;
   uint32_t b = blockIdx.x * kWavesPerBlock + wave_id();
   int m = threadIdx.x & (kWave - 1);
@@ -283,42 +259,106 @@ __global__ void __launch_bounds__(kBlock) k_pcg_Ap(PcgArgs P, const double *p, d
     double c, k0, k1, k2;
     leaf_cell(P, b, m, c, k0, k1, k2);
     double u = p[b * 64u + m];
-    double y = TRANS ? composite_AuT(P.T, P.C, P.TC, p, M, m, u, c, k0, k1, k2)
-                     : composite_Au(P.T, P.C, P.TC, p, M, m, u, c, k0, k1, k2);
+    double y = composite_AuT(P.T, P.C, P.TC, p, M, m, u, c, k0, k1, k2);
     Ap[b * 64u + m] = y;
     part = u * y;
   }
-  __shared__ double red[kWavesPerBlock];
-  part = wave_sum(part);
-  if (m == 0) red[threadIdx.x >> 6] = part;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int w = 0; w < kWavesPerBlock; ++w) s += red[w];
-    P.partials[blockIdx.x] = s;
+  block_partial(part, P.partials);
+}
+
+// Second stage of every PCG reduction: the per-workgroup partials of the
+// preceding kernel (n of them) are added in fixed order by one workgroup,
+// which then updates the solve's scalars.  (A grid-wide "last workgroup"
+// scheme needs a device-scope release per workgroup, which writes back the
+// XCD's L2 each time; a kernel boundary is cheaper.)
+enum FinishOp : int {
+  kFinInit = 0,   // ||r_0||^2: tolerance, first history entry
+  kFinRz = 1,     // (r, z): beta (arg = 1 on the first iteration)
+  kFinAlpha = 2,  // (p, Ap): alpha
+  kFinUpdate = 3, // ||r_k||^2: stop test
+  kFinTrue = 4,   // ||rhs - A x||^2
+  kFinSum = 5,    // sum over active cells (null-space mean)
+  kFinShift = 6,  // ||v||^2 after the mean shift, arg = mode of k_shift_mean
+};
+
+__device__ __forceinline__ void finish_iteration(const PcgArgs &P, double tot) {
+  Scalars *S = P.S;
+  S->rr = tot;
+  S->iters += 1;
+  P.hist[S->iters] = S->rr0 > 0.0 ? sqrt(tot / S->rr0) : 0.0;
+  if (!(tot < INFINITY)) {
+    S->status = -5;
+    S->done = 1;
+  } else if (tot <= S->tol2) {
+    S->done = 1;
   }
 }
 
-// (p, Ap) from the per-workgroup partials in fixed order; alpha = (r,z)/(p,Ap)
-__global__ void __launch_bounds__(1024) k_finish_alpha(PcgArgs P, int64_t n) {
-  if (P.S->done) return;
+__device__ __forceinline__ void finish_initial(const PcgArgs &P, double tot, double rtol) {
+  Scalars *S = P.S;
+  S->rr0 = tot;
+  S->rr = tot;
+  S->tol2 = rtol * rtol * tot;
+  S->iters = 0;
+  S->status = 0;
+  S->done = (tot == 0.0) || !(tot < INFINITY);
+  if (!(tot < INFINITY)) S->status = -5;
+  S->rz = 0.0;
+  P.hist[0] = tot > 0.0 ? 1.0 : 0.0;
+}
+
+__global__ void __launch_bounds__(1024) k_finish(PcgArgs P, int64_t n, int op, int arg,
+                                                 double rtol) {
+  Scalars *S = P.S;
+  // the reductions of a stopped solve were skipped by their kernels
+  bool gated = op == kFinRz || op == kFinAlpha || op == kFinUpdate ||
+               (op == kFinShift && arg == 1);
+  if (gated && S->done) return;
   __shared__ double red[16];
   double s = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += P.partials[i];
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double tot = 0.0;
-    for (unsigned w = 0; w < blockDim.x / 64; ++w) tot += red[w];
-    Scalars *S = P.S;
-    S->pAp = tot;
-    if (!(tot > 0.0) || !(tot < INFINITY)) {
-      S->status = -5;
-      S->done = 1;
-    } else {
-      S->alpha = S->rz / tot;
-    }
+  if (threadIdx.x != 0) return;
+  double tot = 0.0;
+  for (unsigned w = 0; w < blockDim.x / 64; ++w) tot += red[w];
+  switch (op) {
+    case kFinInit:
+      finish_initial(P, tot, rtol);
+      break;
+    case kFinRz:
+      if (!(tot > 0.0) || !(tot < INFINITY)) {
+        S->status = -5;
+        S->done = 1;
+      } else {
+        S->beta = arg ? 0.0 : tot / S->rz;
+        S->rz = tot;
+      }
+      break;
+    case kFinAlpha:
+      S->pAp = tot;
+      if (!(tot > 0.0) || !(tot < INFINITY)) {
+        S->status = -5;
+        S->done = 1;
+      } else {
+        S->alpha = S->rz / tot;
+      }
+      break;
+    case kFinUpdate:
+      finish_iteration(P, tot);
+      break;
+    case kFinTrue:
+      S->tr = tot;
+      break;
+    case kFinSum:
+      S->sum = tot;
+      break;
+    case kFinShift:
+      if (arg == 0) finish_initial(P, tot, rtol);
+      else if (arg == 1) finish_iteration(P, tot);
+      else if (arg == 2) S->tr = tot;
+      break;
   }
 }
 
@@ -353,19 +393,8 @@ __global__ void __launch_bounds__(kBlock) k_pcg_update(PcgArgs P, double *x, dou
     }
     part += rv.x * rv.x + rv.y * rv.y;
   }
-  Scalars *S = P.S;
   if (defer) return;  // the null-space shift completes this step
-  block_reduce_finish(part, P.partials, &S->ticket[3], [&](double tot) {
-    S->rr = tot;
-    S->iters += 1;
-    P.hist[S->iters] = S->rr0 > 0.0 ? sqrt(tot / S->rr0) : 0.0;
-    if (!(tot < INFINITY)) {
-      S->status = -5;
-      S->done = 1;
-    } else if (tot <= S->tol2) {
-      S->done = 1;
-    }
-  });
+  block_partial(part, P.partials);
 }
 
 // X (full size, device order) from a leaf vector x; canonical = 1 when x is
@@ -382,34 +411,46 @@ __global__ void __launch_bounds__(kBlock) k_full(PcgArgs P, const double *x, dou
   }
 }
 
-// y = A X (X from k_full) or y = A^T X, y in device order
-template <bool TRANS>
+// y = A X (X from k_full), y in device order (wave_loop grid)
 __global__ void __launch_bounds__(kBlock) k_apply(PcgArgs P, const double *X, double *y) {
+  const LevelView<double, double, double> V = composite_view(P, X);
+  const LaneC<double, double> L = lane_consts<double, double>();
+  const __amdgpu_buffer_rsrc_t out = make_rsrc(y, uint64_t(P.T.nlb) * 64 * sizeof(double));
+  const WaveLoop W = wave_loop(P.T.nlb);
+  for (uint32_t b = W.first; b < W.end; b += W.step) {
+    double u;
+    double v = composite_row(V, L, b, u);
+    bstore<double>(out, L.m, b * 64u, v);
+  }
+}
+
+// y = A^T X, y in device order
+__global__ void __launch_bounds__(kBlock) k_applyT(PcgArgs P, const double *X, double *y) {
   LEAF_LOOP(P) {
     const BrickMeta M = P.T.meta[b];
     double c, k0, k1, k2;
     leaf_cell(P, b, m, c, k0, k1, k2);
     double u = X[b * 64u + m];
-    y[b * 64u + m] = TRANS ? composite_AuT(P.T, P.C, P.TC, X, M, m, u, c, k0, k1, k2)
-                           : composite_Au(P.T, P.C, P.TC, X, M, m, u, c, k0, k1, k2);
+    y[b * 64u + m] = composite_AuT(P.T, P.C, P.TC, X, M, m, u, c, k0, k1, k2);
   }
 }
 
-// ||rhs - A X||^2 over active cells, rhs in canonical order
+// ||rhs - A X||^2 over active cells, rhs in canonical order (wave_loop grid)
 __global__ void __launch_bounds__(kBlock) k_true_resid(PcgArgs P, const double *rhs,
                                                        const double *X) {
+  const LevelView<double, double, double> V = composite_view(P, X);
+  const LaneC<double, double> L = lane_consts<double, double>();
+  const WaveLoop W = wave_loop(P.T.nlb);
   double part = 0.0;
-  LEAF_LOOP(P) {
-    const BrickMeta M = P.T.meta[b];
-    double c, k0, k1, k2;
-    leaf_cell(P, b, m, c, k0, k1, k2);
-    double y = composite_Au(P.T, P.C, P.TC, X, M, m, X[b * 64u + m], c, k0, k1, k2);
-    bool act = (act_mask(M) >> m) & 1ull;
-    double t = act ? rhs[uint32_t(P.canon[b]) * 64u + m] - y : 0.0;
+  for (uint32_t b = W.first; b < W.end; b += W.step) {
+    double u;
+    double y = composite_row(V, L, b, u);
+    const BrickMeta M = load_meta(P.T.meta, b);
+    bool act = (act_mask(M) >> L.m) & 1ull;
+    double t = act ? rhs[uint32_t(P.canon[b]) * 64u + L.m] - y : 0.0;
     part += t * t;
   }
-  Scalars *S = P.S;
-  block_reduce_finish(part, P.partials, &S->ticket[0], [&](double tot) { S->tr = tot; });
+  block_partial(part, P.partials);
 }
 
 // device-order leaf vector of type V -> canonical FP64 (inactive cells 0)
@@ -438,8 +479,7 @@ __global__ void __launch_bounds__(kBlock) k_sum_active(PcgArgs P, const double *
     const BrickMeta M = P.T.meta[b];
     if ((act_mask(M) >> m) & 1ull) part += v[b * 64u + m];
   }
-  Scalars *S = P.S;
-  block_reduce_finish(part, P.partials, &S->ticket[1], [&](double tot) { S->sum = tot; });
+  block_partial(part, P.partials);
 }
 
 // v -= sum / n_active on active cells and ||v||^2; mode 0: initial residual
@@ -447,7 +487,7 @@ __global__ void __launch_bounds__(kBlock) k_sum_active(PcgArgs P, const double *
 // residual (tr), 3: solution (no norm)
 template <class V>
 __global__ void __launch_bounds__(kBlock) k_shift_mean(PcgArgs P, double *v, V *v_low,
-                                                       double n_active, int mode, double rtol) {
+                                                       double n_active, int mode) {
   if (mode == 1 && P.S->done) return;
   double mean = P.S->sum / n_active;
   double part = 0.0;
@@ -459,41 +499,21 @@ __global__ void __launch_bounds__(kBlock) k_shift_mean(PcgArgs P, double *v, V *
     if (v_low) v_low[i] = V(x);
     part += x * x;
   }
-  Scalars *S = P.S;
-  block_reduce_finish(part, P.partials, &S->ticket[2], [&](double tot) {
-    if (mode == 0) {
-      S->rr0 = tot;
-      S->rr = tot;
-      S->tol2 = rtol * rtol * tot;
-      S->done = (tot == 0.0) || !(tot < INFINITY);
-      if (!(tot < INFINITY)) S->status = -5;
-      P.hist[0] = tot > 0.0 ? 1.0 : 0.0;
-    } else if (mode == 1) {
-      S->rr = tot;
-      S->iters += 1;
-      P.hist[S->iters] = S->rr0 > 0.0 ? sqrt(tot / S->rr0) : 0.0;
-      if (!(tot < INFINITY)) {
-        S->status = -5;
-        S->done = 1;
-      } else if (tot <= S->tol2) {
-        S->done = 1;
-      }
-    } else if (mode == 2) {
-      S->tr = tot;
-    }
-  });
+  block_partial(part, P.partials);
 }
 
-// t = rhs - A X over active cells (device order), rhs canonical
+// t = rhs - A X over active cells (device order), rhs canonical (wave_loop grid)
 __global__ void __launch_bounds__(kBlock) k_residual_vec(PcgArgs P, const double *rhs,
                                                          const double *X, double *t) {
-  LEAF_LOOP(P) {
-    const BrickMeta M = P.T.meta[b];
-    double c, k0, k1, k2;
-    leaf_cell(P, b, m, c, k0, k1, k2);
-    double y = composite_Au(P.T, P.C, P.TC, X, M, m, X[b * 64u + m], c, k0, k1, k2);
-    bool act = (act_mask(M) >> m) & 1ull;
-    t[b * 64u + m] = act ? rhs[uint32_t(P.canon[b]) * 64u + m] - y : 0.0;
+  const LevelView<double, double, double> V = composite_view(P, X);
+  const LaneC<double, double> L = lane_consts<double, double>();
+  const WaveLoop W = wave_loop(P.T.nlb);
+  for (uint32_t b = W.first; b < W.end; b += W.step) {
+    double u;
+    double y = composite_row(V, L, b, u);
+    const BrickMeta M = load_meta(P.T.meta, b);
+    bool act = (act_mask(M) >> L.m) & 1ull;
+    t[b * 64u + L.m] = act ? rhs[uint32_t(P.canon[b]) * 64u + L.m] - y : 0.0;
   }
 }
 
