@@ -191,7 +191,9 @@ def main():
     del beta
     t0 = time.perf_counter()
     co = mfmg.assemble_coeffs(tree, beta_d, bc, theta)
-    nact = int((co.leaf_coeffs()[0] != 0).sum().item())
+    act_d = co.leaf_coeffs()[0] != 0
+    nact = int(act_d.sum().item())
+    act = act_d.cpu().numpy()
     L = spec["max_level"]
     if args.traffic_pass:
         h = mfmg.build_hierarchy(co, precision=mfmg.MIXED)
@@ -225,16 +227,32 @@ def main():
         st = stats[-1]
         ms_s, by_s = mfmg.profile(h, mfmg.PROFILE_SMOOTH, L, reps=50)
         ms_c, by_c = mfmg.profile(h, mfmg.PROFILE_CYCLE, 0, reps=10)
+        ms_cp, by_cp = mfmg.profile(h, mfmg.PROFILE_COPY, 0, reps=20)
+        # adjoint of L = ||p - p_t||^2 at this solution (outside the timed region)
+        pn = p.cpu().numpy()
+        pt = problems.adjoint_target(lev, ijk, np.abs(pn).max())
+        g_d = dev(np.where(act, 2.0 * (pn - pt), 0.0))
+        mfmg.pcg_solve_adjoint(h, p, g_d, rtol=1e-10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, ast = mfmg.pcg_solve_adjoint(h, p, g_d, rtol=1e-10)
+        torch.cuda.synchronize()
+        dt_adj = time.perf_counter() - t0
         out[name] = {"ms_per_solve": dt * 1e3, "mcells_per_s": nact / dt / 1e6,
                      "iters": st["iters"], "rel_resid_true": st["rel_resid_true"],
                      "device_ms_per_solve": st["seconds"] * 1e3,
                      "smooth_ms": ms_s, "smooth_bytes": by_s,
                      "smooth_gbs": by_s / ms_s / 1e6,
-                     "cycle_ms": ms_c, "cycle_bytes": by_c, "cycle_gbs": by_c / ms_c / 1e6}
+                     "cycle_ms": ms_c, "cycle_bytes": by_c, "cycle_gbs": by_c / ms_c / 1e6,
+                     "copy_gbs": by_cp / ms_cp / 1e6,
+                     "adjoint_ms": dt_adj * 1e3, "adjoint_iters": ast["iters"],
+                     "adjoint_rel_resid_true": ast["rel_resid_true"]}
         log(f"[bench] {name}: {dt * 1e3:.2f} ms/solve, {st['iters']} iterations, "
             f"true residual {st['rel_resid_true']:.2e}, {nact / dt / 1e6:.1f} Mcells/s; "
             f"finest half-sweep {ms_s * 1e3:.1f} us = {by_s / ms_s / 1e6:.0f} GB/s; "
-            f"cycle {ms_c:.3f} ms = {by_c / ms_c / 1e6:.0f} GB/s")
+            f"cycle {ms_c:.3f} ms = {by_c / ms_c / 1e6:.0f} GB/s; "
+            f"streaming copy {by_cp / ms_cp / 1e6:.0f} GB/s; adjoint solve + gradient "
+            f"{dt_adj * 1e3:.1f} ms ({ast['iters']} iterations)")
     head = out["mixed"]
     traffic = measured_traffic("mixed", L)
     roof = {"bound": "hbm", "achieved": head["smooth_gbs"], "peak": HBM_PEAK_GBS,
@@ -242,7 +260,9 @@ def main():
             "traffic": traffic,
             "kernel": f"k_smooth<float,float,__half> colour half-sweep, level {L}",
             "algorithmic_bytes_per_launch": head["smooth_bytes"],
-            "avg_launch_us": head["smooth_ms"] * 1e3}
+            "avg_launch_us": head["smooth_ms"] * 1e3,
+            "stream_copy_gbs": head["copy_gbs"],
+            "frac_of_stream_copy": head["smooth_gbs"] / head["copy_gbs"]}
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample ...")
@@ -272,9 +292,12 @@ def main():
         },
         "fp64": {"value": out["fp64"]["mcells_per_s"], "ms_per_step": out["fp64"]["ms_per_solve"],
                  "iters": out["fp64"]["iters"], "rel_resid_true": out["fp64"]["rel_resid_true"],
-                 "vcycle_gbs": out["fp64"]["cycle_gbs"]},
+                 "vcycle_gbs": out["fp64"]["cycle_gbs"], "vcycle_ms": out["fp64"]["cycle_ms"],
+                 "adjoint_ms": out["fp64"]["adjoint_ms"],
+                 "adjoint_iters": out["fp64"]["adjoint_iters"]},
         "mixed": {"iters": head["iters"], "rel_resid_true": head["rel_resid_true"],
-                  "vcycle_gbs": head["cycle_gbs"], "vcycle_ms": head["cycle_ms"]},
+                  "vcycle_gbs": head["cycle_gbs"], "vcycle_ms": head["cycle_ms"],
+                  "adjoint_ms": head["adjoint_ms"], "adjoint_iters": head["adjoint_iters"]},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

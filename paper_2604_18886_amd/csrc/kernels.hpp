@@ -273,7 +273,12 @@ __global__ void __launch_bounds__(kBlock) k_convert_inner(const double *coef, To
 // a * 16 + f is the coefficient of the face between the brick's cell on its
 // +a side with face index f and what lies beyond it -- the same-level
 // neighbour's k_a (in mixed precision rounded exactly as the neighbour's own
-// coefficients are stored), the T-face coefficient K_F, or 0 at a wall.
+// coefficients are stored), or the T-face coefficient K_F.  At a +a domain
+// wall it is the part of the cell's diagonal not carried by its other five
+// faces (the wall's coefficient; 0 at a Neumann wall), so that for every cell
+// the diagonal is the sum of the six face coefficients the stencil sees
+// (Eq. 3; Algorithm 3 keeps this on every level).  A cell on several +walls
+// carries that part on the first of them.
 template <class CL>
 __global__ void __launch_bounds__(kBlock) k_plus_faces(Topo T, const double *coef,
                                                        const double *tc, CL *pf, int half_inner) {
@@ -286,18 +291,39 @@ __global__ void __launch_bounds__(kBlock) k_plus_faces(Topo T, const double *coe
   c[a == 0 ? 1 : 0] = f & 3;
   c[a == 2 ? 1 : 2] = f >> 2;
   int m = dev_morton(c[0], c[1], c[2]);
-  int d = 2 * a + 1;
   const BrickMeta M = T.meta[b];
-  int32_t n = M.nbr[d];
-  double v = 0.0;
-  if (n >= 0) {
-    v = coef[uint32_t(n) * 256u + (1 + a) * 64 + dev_partner(m, d)];
-    if (half_inner && uint32_t(n) >= T.nlb) {
-      float hv = __half2float(__float2half_rn(float(v * ldexp(1.0, M.level))));
-      v = double(hv * ldexpf(1.0f, -M.level));
+  const double *own = coef + uint64_t(b) * 256u;
+  double kp[3];
+  bool wall[3];
+  bool inner_nbr = false;
+  for (int ax = 0; ax < 3; ++ax) {
+    int dd = 2 * ax + 1;
+    kp[ax] = 0.0;
+    wall[ax] = false;
+    int p = dev_partner(m, dd);
+    if (!dev_outside(m, dd)) {
+      kp[ax] = own[(1 + ax) * 64 + p];
+      continue;
     }
-  } else if ((M.flags >> d) & 1u) {
-    v = tc[uint32_t(M.tplus) * 48u + a * 16 + f];
+    int32_t n = M.nbr[dd];
+    if (n >= 0) {
+      kp[ax] = coef[uint64_t(n) * 256u + (1 + ax) * 64 + p];
+      if (ax == a) inner_nbr = uint32_t(n) >= T.nlb;
+    } else if ((M.flags >> dd) & 1u) {
+      kp[ax] = tc[uint32_t(M.tplus) * 48u + ax * 16 + dev_face_index(m, ax)];
+    } else {
+      wall[ax] = true;
+    }
+  }
+  double v = kp[a];
+  if (wall[a]) {
+    int first = wall[0] ? 0 : (wall[1] ? 1 : 2);
+    v = first == a ? own[m] - (own[64 + m] + own[128 + m] + own[192 + m]) -
+                         (kp[0] + kp[1] + kp[2])
+                   : 0.0;
+  } else if (half_inner && inner_nbr) {
+    float hv = __half2float(__float2half_rn(float(v * ldexp(1.0, M.level))));
+    v = double(hv * ldexpf(1.0f, -M.level));
   }
   pf[b * 48u + e] = CL(v);
 }
@@ -430,11 +456,13 @@ __device__ __forceinline__ T bload_bytes(__amdgpu_buffer_rsrc_t r, uint32_t voff
 // the brick, the brick's plus-face array across its faces).  The loads
 // across a face are issued by every lane with an offset that is out of
 // range for the inner lanes and, at a wall or T-face, for all lanes, so
-// the only branch is a scalar one around the T-junction ghosts.
+// the only branch is a scalar one around the T-junction ghosts.  diag
+// returns c_m as the sum of the six face coefficients (see k_plus_faces),
+// so the diagonal is not streamed from memory.
 template <class V, class CL, class CI>
 __device__ __forceinline__ V stencil_sum(const LevelView<V, CL, CI> &X, const LaneC<V, CL> &L,
                                          uint32_t b, const BrickMeta &M, V u, V k0, V k1,
-                                         V k2) {
+                                         V k2, V &diag) {
   V v[6], k[6];
 #pragma unroll
   for (int d = 0; d < 6; ++d) {
@@ -470,6 +498,7 @@ __device__ __forceinline__ V stencil_sum(const LevelView<V, CL, CI> &X, const La
       }
     }
   }
+  diag = ((k[0] + k[1]) + (k[2] + k[3])) + (k[4] + k[5]);
   V acc = V(0);
 #pragma unroll
   for (int d = 0; d < 6; ++d) acc += k[d] * v[d];
@@ -483,13 +512,13 @@ template <bool INNER, class V, class CL, class CI>
 __device__ __forceinline__ void smooth_brick(const LevelView<V, CL, CI> &X, const LaneC<V, CL> &L,
                                              uint32_t b, int colour) {
   const BrickMeta M = load_meta(X.meta, b);
-  V c = own_coef<INNER>(X, b, 0, L.m);
   V k0 = own_coef<INNER>(X, b, 1, L.m);
   V k1 = own_coef<INNER>(X, b, 2, L.m);
   V k2 = own_coef<INNER>(X, b, 3, L.m);
   V u = bload<V>(X.u, L.m, b * 64u);
   V rhs = bload<V>(X.b, L.m, b * 64u);
-  V S = stencil_sum(X, L, b, M, u, k0, k1, k2);
+  V c;
+  V S = stencil_sum(X, L, b, M, u, k0, k1, k2, c);
   bool act = (act_mask(M) >> L.m) & 1ull;
   if (act && L.colour == colour) bstore<V>(X.u, L.m, b * 64u, div_by(rhs + S, c));
 }
@@ -534,13 +563,13 @@ template <bool INNER, class V, class CL, class CI>
 __device__ __forceinline__ void restrict_brick(const LevelView<V, CL, CI> &X, const LaneC<V, CL> &L,
                                                uint32_t b, V scale) {
   const BrickMeta M = load_meta(X.meta, b);
-  V c = own_coef<INNER>(X, b, 0, L.m);
   V k0 = own_coef<INNER>(X, b, 1, L.m);
   V k1 = own_coef<INNER>(X, b, 2, L.m);
   V k2 = own_coef<INNER>(X, b, 3, L.m);
   V u = bload<V>(X.u, L.m, b * 64u);
   V rhs = bload<V>(X.b, L.m, b * 64u);
-  V S = stencil_sum(X, L, b, M, u, k0, k1, k2);
+  V c;
+  V S = stencil_sum(X, L, b, M, u, k0, k1, k2, c);
   uint64_t amask = act_mask(M);
   bool act = (amask >> L.m) & 1ull;
   V r = act ? rhs - (c * u - S) : V(0);
@@ -579,13 +608,13 @@ __global__ void __launch_bounds__(kBlock) k_fas_rhs(LevelArgs<V, CL, CI> A) {
   for (uint32_t i = W.first; i < W.end; i += W.step) {
     uint32_t b = A.R.inner_lo + i;
     const BrickMeta M = load_meta(X.meta, b);
-    V c = own_coef<true>(X, b, 0, L.m);
     V k0 = own_coef<true>(X, b, 1, L.m);
     V k1 = own_coef<true>(X, b, 2, L.m);
     V k2 = own_coef<true>(X, b, 3, L.m);
     V u = bload<V>(X.u, L.m, b * 64u);
     V rhs = bload<V>(X.b, L.m, b * 64u);
-    V S = stencil_sum(X, L, b, M, u, k0, k1, k2);
+    V c;
+    V S = stencil_sum(X, L, b, M, u, k0, k1, k2, c);
     bool act = (act_mask(M) >> L.m) & 1ull;
     bstore<V>(X.b, L.m, b * 64u, act ? rhs + (c * u - S) : V(0));
   }

@@ -164,9 +164,12 @@ struct mfmg_hierarchy {
   DevBuf<int64_t> f_owner, f_other;
   DevBuf<int8_t> f_dir, f_kind, leaf_level;
   DevBuf<uint64_t> canon_act;
-  Scalars *hostS = nullptr;      // pinned
+  Scalars *hostS = nullptr;      // pinned, 3 slots: [0] final read, [1..2] per-iteration checks
+  hipEvent_t iter_ev[2] = {nullptr, nullptr};
   ~mfmg_hierarchy() {
     if (hostS) (void)hipHostFree(hostS);
+    for (hipEvent_t e : iter_ev)
+      if (e) (void)hipEventDestroy(e);
   }
 };
 
@@ -500,7 +503,9 @@ extern "C" mfmg_status mfmg_build_hierarchy(const mfmg_coeffs *co, const mfmg_mg
                                          int64_t(level_grid(nlb))}));
     h->S.alloc(1);
     HIP_CHECK(hipMemsetAsync(h->S.p, 0, sizeof(Scalars), s));
-    HIP_CHECK(hipHostMalloc(&h->hostS, sizeof(Scalars), hipHostMallocDefault));
+    HIP_CHECK(hipHostMalloc(&h->hostS, 3 * sizeof(Scalars), hipHostMallocDefault));
+    for (hipEvent_t &e : h->iter_ev)
+      HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     // active leaf count (for the null-space mean)
     std::vector<BrickMeta> mh(nlb);
     HIP_CHECK(hipMemcpyAsync(mh.data(), h->meta.p, size_t(nlb) * sizeof(BrickMeta),
@@ -965,9 +970,16 @@ static void pcg_iterate(mfmg_hierarchy *h, const double *rhs, double *r, V *r_lo
     run_cycle(h, s, done);
     K.rz(r, z, 0);
     K.pupdate(z, 0);
-    HIP_CHECK(hipMemcpyAsync(h->hostS, h->S.p, sizeof(Scalars), hipMemcpyDeviceToHost, s));
-    HIP_CHECK(hipStreamSynchronize(s));
-    if (h->hostS->done) break;
+    // The stop flag of iteration it is read on the host only after
+    // iteration it + 1 is queued, so the GPU never idles on the round trip;
+    // every kernel of an iteration queued after the stop returns at once.
+    Scalars *slot = h->hostS + 1 + (it & 1);
+    HIP_CHECK(hipMemcpyAsync(slot, h->S.p, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipEventRecord(h->iter_ev[it & 1], s));
+    if (it > 0) {
+      HIP_CHECK(hipEventSynchronize(h->iter_ev[(it - 1) & 1]));
+      if (h->hostS[1 + ((it - 1) & 1)].done) break;
+    }
   }
   // zero-mean solution, then the true residual shifted to zero mean
   if (null_space) R.shift_mean<double>(x, (double *)nullptr, na, 3, 0.0);
@@ -1257,6 +1269,8 @@ extern "C" mfmg_status mfmg_profile(mfmg_hierarchy *h, int what, int level, int 
   hipStream_t s = (hipStream_t)stream;
   if (what == MFMG_PROFILE_SMOOTH && (level < h->lc || level > h->L))
     return fail(MFMG_ERR_INVALID_ARG, "level out of range");
+  if (what < MFMG_PROFILE_SMOOTH || what > MFMG_PROFILE_COPY)
+    return fail(MFMG_ERR_INVALID_ARG, "unknown profile step");
   try {
     hipEvent_t e0, e1;
     HIP_CHECK(hipEventCreate(&e0));
@@ -1275,8 +1289,12 @@ extern "C" mfmg_status mfmg_profile(mfmg_hierarchy *h, int what, int level, int 
                                           nullptr, s};
           c.half_sweep(c.args(level, false), 0);
         }
-      } else {
+      } else if (what == MFMG_PROFILE_CYCLE) {
         run_cycle(h, s, nullptr);
+      } else {
+        int64_t n4 = int64_t(h->co->dt->nlb) * 16;  // groups of four doubles
+        hipLaunchKernelGGL(k_stream_copy, dim3(grid_elems(n4, 256 * 4)), dim3(256), 0, s,
+                           (const double4 *)h->x.p, (double4 *)h->Ap.p, n4);
       }
     };
     launch();  // warm
@@ -1290,7 +1308,10 @@ extern "C" mfmg_status mfmg_profile(mfmg_hierarchy *h, int what, int level, int 
     (void)hipEventDestroy(e1);
     *ms_per_launch = double(ms) / reps;
     if (bytes_per_launch)
-      *bytes_per_launch = what == MFMG_PROFILE_SMOOTH ? smooth_bytes(h, level) : cycle_bytes(h);
+      *bytes_per_launch = what == MFMG_PROFILE_SMOOTH ? smooth_bytes(h, level)
+                          : what == MFMG_PROFILE_CYCLE
+                              ? cycle_bytes(h)
+                              : 2.0 * double(h->co->dt->nlb) * 64 * sizeof(double);
   } catch (const HipError &e) {
     return fail(MFMG_ERR_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
   }

@@ -132,12 +132,12 @@ __device__ __forceinline__ double composite_row(const LevelView<double, double, 
                                                 const LaneC<double, double> &L, uint32_t b,
                                                 double &u) {
   const BrickMeta M = load_meta(V.meta, b);
-  double c = own_coef<false>(V, b, 0, L.m);
   double k0 = own_coef<false>(V, b, 1, L.m);
   double k1 = own_coef<false>(V, b, 2, L.m);
   double k2 = own_coef<false>(V, b, 3, L.m);
   u = bload<double>(V.u, L.m, b * 64u);
-  double S = stencil_sum(V, L, b, M, u, k0, k1, k2);
+  double c;
+  double S = stencil_sum(V, L, b, M, u, k0, k1, k2, c);
   bool act = (act_mask(M) >> L.m) & 1ull;
   return act ? c * u - S : 0.0;
 }
@@ -515,6 +515,20 @@ __global__ void __launch_bounds__(kBlock) k_residual_vec(PcgArgs P, const double
     bool act = (act_mask(M) >> L.m) & 1ull;
     t[b * 64u + L.m] = act ? rhs[uint32_t(P.canon[b]) * 64u + L.m] - y : 0.0;
   }
+}
+
+// Streaming copy (measurement of the achievable HBM bandwidth): each thread
+// moves four 32-byte groups, all loads issued before the stores.
+__global__ void __launch_bounds__(256) k_stream_copy(const double4 *__restrict__ src,
+                                                     double4 *__restrict__ dst, int64_t n) {
+  int64_t i = (int64_t(blockIdx.x) * 4) * blockDim.x + threadIdx.x;
+  double4 v[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (i + k * blockDim.x < n) v[k] = src[i + k * blockDim.x];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (i + k * blockDim.x < n) dst[i + k * blockDim.x] = v[k];
 }
 
 // ---------------------------------------------------------------------------

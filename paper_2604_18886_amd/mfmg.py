@@ -336,7 +336,7 @@ def apply_precond(h, r, transpose=False):
     return z
 
 
-PROFILE_SMOOTH, PROFILE_CYCLE = 0, 1
+PROFILE_SMOOTH, PROFILE_CYCLE, PROFILE_COPY = 0, 1, 2
 
 
 def profile(h, what, level=0, reps=20):

@@ -138,3 +138,30 @@ def test_null_space_all_neumann():
     assert st["status"] == 0
     assert abs(p[act].mean()) <= 1e-12 * np.abs(p).max()
     assert rel(p, x) <= 1e-9
+
+
+@pytest.mark.parametrize("mu", [2])
+def test_w_cycle_matches_oracle(mu):
+    """The mu-cycle (Algorithm 4 with mu recursive coarse solves; mu = 2 is
+    the W-cycle the paper uses on cut-cell grids): one cycle and a full
+    solve against the oracle's."""
+    import problems
+    from gpu_fixtures import Case
+    from oracle import krylov as K
+    from oracle import multigrid as M
+    from paper_2604_18886_amd import mfmg
+    case = Case(3, problems.config_spec(3, 5, 7))
+    H = M.Hierarchy(case.disc, coarsest=3, mu=mu)
+    h = case.gpu_hierarchy(mu=mu)
+    rng = np.random.default_rng(10)
+    r = np.where(case.disc.active, rng.uniform(-1, 1, case.T.n), 0.0)
+    z = mfmg.apply_precond(h, case.device(r)).cpu().numpy()
+    assert rel(z, H.vcycle(r)) <= 1e-12
+    p, st = mfmg.pcg_solve(h, case.device(case.rhs), rtol=1e-10)
+    x, info = K.pcg(case.disc.A, case.rhs, H.vcycle, 1e-13, 400, active=case.disc.active)
+    _, info10 = K.pcg(case.disc.A, case.rhs, H.vcycle, 1e-10, 400, active=case.disc.active)
+    print(f"  mu={mu}: gpu iters={st['iters']} oracle(1e-10)={info10['iters']} "
+          f"err={rel(p.cpu().numpy(), x):.2e}", flush=True)
+    assert st["status"] == 0
+    assert abs(st["iters"] - info10["iters"]) <= 1
+    assert rel(p.cpu().numpy(), x) <= 1e-9
