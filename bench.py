@@ -43,8 +43,10 @@ def log(*a):
 
 
 def kernel_source_hash():
+    """Hash of the sources that define the level kernels (the dominant one
+    and everything it calls)."""
     h = hashlib.sha256()
-    for f in ("kernels.hpp", "device.hpp", "mfmg.hip"):
+    for f in ("kernels.hpp", "device.hpp"):
         with open(os.path.join(ROOT, "paper_2604_18886_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -107,7 +109,7 @@ def summarize_pmc(fetch_csv, write_csv, level):
     return rec
 
 
-def cpu_baseline(sample_levels=(5, 8)):
+def cpu_baseline(sample_levels=(6, 9)):
     """The oracle (test infrastructure) timed on the host, one thread, on a
     smaller member of the same workload family."""
     from threadpoolctl import threadpool_limits

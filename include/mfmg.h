@@ -247,9 +247,10 @@ mfmg_status mfmg_apply_precond(mfmg_hierarchy *h, const double *r, double *z,
  *   what = MFMG_PROFILE_SMOOTH: one colour half-sweep of level `level`;
  *   what = MFMG_PROFILE_CYCLE:  one whole cycle (level ignored), its
  *          right-hand side being the current residual buffer;
- *   what = MFMG_PROFILE_COPY:   a plain streaming copy between two FP64
- *          leaf vectors of h (16-byte accesses; bytes = read + write), the
- *          achievable HBM ceiling the other figures are compared with.
+ *   what = MFMG_PROFILE_COPY:   a plain streaming copy of 1 GiB between two
+ *          buffers allocated for the measurement (16-byte accesses; bytes =
+ *          read + write), the achievable HBM ceiling the other figures are
+ *          compared with.
  * The work vectors of h are overwritten. */
 enum { MFMG_PROFILE_SMOOTH = 0, MFMG_PROFILE_CYCLE = 1, MFMG_PROFILE_COPY = 2 };
 mfmg_status mfmg_profile(mfmg_hierarchy *h, int what, int level, int reps,

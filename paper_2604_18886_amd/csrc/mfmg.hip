@@ -164,10 +164,24 @@ struct mfmg_hierarchy {
   DevBuf<int64_t> f_owner, f_other;
   DevBuf<int8_t> f_dir, f_kind, leaf_level;
   DevBuf<uint64_t> canon_act;
-  Scalars *hostS = nullptr;      // pinned, 3 slots: [0] final read, [1..2] per-iteration checks
+  Scalars *hostS = nullptr;      // pinned: the scalars read back after a solve
+  int *host_done = nullptr;      // pinned, mapped: stop flag written by k_finish
+  int *host_done_dev = nullptr;  // its device address
   hipEvent_t iter_ev[2] = {nullptr, nullptr};
+  hipStream_t cap_stream = nullptr;                 // capture-only stream of the graphs
+  hipGraphExec_t iter_graph[2] = {nullptr, nullptr};  // PCG loop body [null space]
+  void drop_graphs() {
+    for (hipGraphExec_t &g : iter_graph)
+      if (g) {
+        (void)hipGraphExecDestroy(g);
+        g = nullptr;
+      }
+  }
   ~mfmg_hierarchy() {
+    drop_graphs();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (hostS) (void)hipHostFree(hostS);
+    if (host_done) (void)hipHostFree(host_done);
     for (hipEvent_t e : iter_ev)
       if (e) (void)hipEventDestroy(e);
   }
@@ -503,7 +517,10 @@ extern "C" mfmg_status mfmg_build_hierarchy(const mfmg_coeffs *co, const mfmg_mg
                                          int64_t(level_grid(nlb))}));
     h->S.alloc(1);
     HIP_CHECK(hipMemsetAsync(h->S.p, 0, sizeof(Scalars), s));
-    HIP_CHECK(hipHostMalloc(&h->hostS, 3 * sizeof(Scalars), hipHostMallocDefault));
+    HIP_CHECK(hipHostMalloc(&h->hostS, sizeof(Scalars), hipHostMallocDefault));
+    HIP_CHECK(hipHostMalloc(&h->host_done, sizeof(int), hipHostMallocMapped));
+    HIP_CHECK(hipHostGetDevicePointer((void **)&h->host_done_dev, h->host_done, 0));
+    *h->host_done = 0;
     for (hipEvent_t &e : h->iter_ev)
       HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     // active leaf count (for the null-space mean)
@@ -799,6 +816,7 @@ PcgArgs pcg_args(mfmg_hierarchy *h) {
   P.S = h->S.p;
   P.partials = h->partials.p;
   P.hist = h->hist.p;
+  P.host_done = h->host_done_dev;
   return P;
 }
 
@@ -922,8 +940,8 @@ struct Krylov {
     n2 = int64_t(h->co->dt->nlb) * 32;
   }
   void rz(const double *r, const V *z, int first) const {
-    hipLaunchKernelGGL(k_pcg_rz<V>, dim3(G), dim3(kBlock), 0, s, P, r, z, n2);
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, P, int64_t(G), int(kFinRz), first,
+    hipLaunchKernelGGL(k_pcg_rz<V>, dim3(GA), dim3(kBlock), 0, s, P, r, z);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, P, int64_t(GA), int(kFinRz), first,
                        0.0);
   }
   void pupdate(const V *z, int first) const {
@@ -948,6 +966,60 @@ struct Krylov {
   }
 };
 
+// Loop body of Algorithm 1 (from A p to the next search direction).
+template <class V>
+static void iteration_body(mfmg_hierarchy *h, double *r, V *r_low, V *z, bool null_space,
+                           hipStream_t s) {
+  Reduce R(h, s);
+  Krylov<V> K(h, s);
+  K.Ap(false);
+  K.update(h->x.p, r, r_low, int(null_space));
+  if (null_space) R.shift_mean<V>(r, r_low, std::max(1.0, h->n_active), 1, 0.0);
+  run_cycle(h, s, &h->S.p->done);
+  K.rz(r, z, 0);
+  K.pupdate(z, 0);
+}
+
+// Launch graphs can be switched off with MFMG_GRAPHS=0 (read once).
+inline bool graphs_enabled() {
+  static const bool on = [] {
+    const char *e = std::getenv("MFMG_GRAPHS");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
+
+// The loop body as one HIP graph, captured once per hierarchy: about a
+// hundred launches, the coarse-level ones only a few microseconds long --
+// shorter than the host needs to issue them one at a time.  Every argument
+// is a pointer or size fixed for the hierarchy (the residual history buffer
+// only grows, and drops the graphs when it does); the body records no
+// memset or copy.  Captured on a private stream, launched on the caller's.
+template <class V>
+static hipGraphExec_t iteration_graph(mfmg_hierarchy *h, double *r, V *r_low, V *z,
+                                      bool null_space) {
+  hipGraphExec_t &ge = h->iter_graph[null_space ? 1 : 0];
+  if (ge) return ge;
+  if (!h->cap_stream) HIP_CHECK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  HIP_CHECK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipGraph_t g = nullptr;
+  try {
+    iteration_body<V>(h, r, r_low, z, null_space, h->cap_stream);
+  } catch (...) {
+    (void)hipStreamEndCapture(h->cap_stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  HIP_CHECK(hipStreamEndCapture(h->cap_stream, &g));
+  hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    ge = nullptr;
+    HIP_CHECK(e);
+  }
+  return ge;
+}
+
 template <class V>
 static void pcg_iterate(mfmg_hierarchy *h, const double *rhs, double *r, V *r_low, V *z,
                         const mfmg_solve_params *sp, bool null_space, hipStream_t s) {
@@ -957,28 +1029,29 @@ static void pcg_iterate(mfmg_hierarchy *h, const double *rhs, double *r, V *r_lo
   const int *done = &h->S.p->done;
   double na = std::max(1.0, h->n_active);
   double *x = h->x.p;
+  __atomic_store_n(h->host_done, 0, __ATOMIC_RELEASE);  // the stream is idle here
   R.init<V>(rhs, r, r_low, x, sp->rtol);
   if (null_space) R.shift_mean<V>(r, r_low, na, 0, sp->rtol);
   Krylov<V> K(h, s);
   run_cycle(h, s, done);
   K.rz(r, z, 1);
   K.pupdate(z, 1);
+  hipGraphExec_t body = graphs_enabled() && sp->max_iter > 0
+                           ? iteration_graph<V>(h, r, r_low, z, null_space)
+                           : nullptr;
   for (int it = 0; it < sp->max_iter; ++it) {
-    K.Ap(false);
-    K.update(x, r, r_low, int(null_space));
-    if (null_space) R.shift_mean<V>(r, r_low, na, 1, sp->rtol);
-    run_cycle(h, s, done);
-    K.rz(r, z, 0);
-    K.pupdate(z, 0);
+    if (body)
+      HIP_CHECK(hipGraphLaunch(body, s));
+    else
+      iteration_body<V>(h, r, r_low, z, null_space, s);
     // The stop flag of iteration it is read on the host only after
     // iteration it + 1 is queued, so the GPU never idles on the round trip;
     // every kernel of an iteration queued after the stop returns at once.
-    Scalars *slot = h->hostS + 1 + (it & 1);
-    HIP_CHECK(hipMemcpyAsync(slot, h->S.p, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+    // k_finish mirrors the flag into mapped host memory (no copy launch).
     HIP_CHECK(hipEventRecord(h->iter_ev[it & 1], s));
     if (it > 0) {
       HIP_CHECK(hipEventSynchronize(h->iter_ev[(it - 1) & 1]));
-      if (h->hostS[1 + ((it - 1) & 1)].done) break;
+      if (__atomic_load_n(h->host_done, __ATOMIC_ACQUIRE)) break;
     }
   }
   // zero-mean solution, then the true residual shifted to zero mean
@@ -1005,7 +1078,10 @@ extern "C" mfmg_status mfmg_pcg_solve(mfmg_hierarchy *h, const double *rhs, doub
   hipStream_t s = (hipStream_t)stream;
   mfmg_status st = MFMG_OK;
   try {
-    h->hist.alloc(size_t(sp->max_iter) + 2);
+    if (h->hist.n < size_t(sp->max_iter) + 2) {
+      h->drop_graphs();  // they hold the old history pointer
+      h->hist.alloc(std::max<size_t>(size_t(sp->max_iter) + 2, 1024));
+    }
     hipEvent_t e0, e1;
     HIP_CHECK(hipEventCreate(&e0));
     HIP_CHECK(hipEventCreate(&e1));
@@ -1102,7 +1178,10 @@ extern "C" mfmg_status mfmg_pcg_solve_adjoint(mfmg_hierarchy *h, const double *p
   const DeviceTopology &D = *h->co->dt;
   mfmg_status st = MFMG_OK;
   try {
-    h->hist.alloc(size_t(sp->max_iter) + 2);
+    if (h->hist.n < size_t(sp->max_iter) + 2) {
+      h->drop_graphs();  // they hold the old history pointer
+      h->hist.alloc(std::max<size_t>(size_t(sp->max_iter) + 2, 1024));
+    }
     if (!h->rA.p) h->rA.alloc(size_t(D.nlb) * 64);
     if (!h->f_owner.p) {
       // canonical face list and per-brick tables for the gradient
@@ -1262,6 +1341,8 @@ double cycle_bytes(const mfmg_hierarchy *h) {
 
 }  // namespace
 
+constexpr size_t kCopyBytes = size_t(1) << 30;
+
 extern "C" mfmg_status mfmg_profile(mfmg_hierarchy *h, int what, int level, int reps,
                                     void *stream, double *ms_per_launch,
                                     double *bytes_per_launch) {
@@ -1276,6 +1357,12 @@ extern "C" mfmg_status mfmg_profile(mfmg_hierarchy *h, int what, int level, int 
     HIP_CHECK(hipEventCreate(&e0));
     HIP_CHECK(hipEventCreate(&e1));
     bool mixed = h->prm.precision == MFMG_MIXED;
+    DevBuf<char> copy_src, copy_dst;  // 1 GiB each, only for the copy
+    if (what == MFMG_PROFILE_COPY) {
+      copy_src.alloc(kCopyBytes);
+      copy_dst.alloc(kCopyBytes);
+      HIP_CHECK(hipMemsetAsync(copy_src.p, 1, kCopyBytes, s));
+    }
     auto launch = [&]() {
       if (what == MFMG_PROFILE_SMOOTH) {
         if (mixed) {
@@ -1292,9 +1379,9 @@ extern "C" mfmg_status mfmg_profile(mfmg_hierarchy *h, int what, int level, int 
       } else if (what == MFMG_PROFILE_CYCLE) {
         run_cycle(h, s, nullptr);
       } else {
-        int64_t n4 = int64_t(h->co->dt->nlb) * 16;  // groups of four doubles
-        hipLaunchKernelGGL(k_stream_copy, dim3(grid_elems(n4, 256 * 4)), dim3(256), 0, s,
-                           (const double4 *)h->x.p, (double4 *)h->Ap.p, n4);
+        int64_t n16 = int64_t(kCopyBytes / 16);
+        hipLaunchKernelGGL(k_stream_copy, dim3(grid_elems(n16, 1024)), dim3(256), 0, s,
+                           (const f32x4 *)copy_src.p, (f32x4 *)copy_dst.p, n16);
       }
     };
     launch();  // warm
@@ -1309,9 +1396,8 @@ extern "C" mfmg_status mfmg_profile(mfmg_hierarchy *h, int what, int level, int 
     *ms_per_launch = double(ms) / reps;
     if (bytes_per_launch)
       *bytes_per_launch = what == MFMG_PROFILE_SMOOTH ? smooth_bytes(h, level)
-                          : what == MFMG_PROFILE_CYCLE
-                              ? cycle_bytes(h)
-                              : 2.0 * double(h->co->dt->nlb) * 64 * sizeof(double);
+                          : what == MFMG_PROFILE_CYCLE ? cycle_bytes(h)
+                                                       : 2.0 * double(kCopyBytes);
   } catch (const HipError &e) {
     return fail(MFMG_ERR_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
   }

@@ -18,6 +18,7 @@ struct PcgArgs {
   Scalars *S;
   double *partials;
   double *hist;
+  int *host_done;        // pinned host copy of S->done (mapped), or null
 };
 
 __device__ __forceinline__ void leaf_cell(const PcgArgs &P, uint32_t b, int m, double &c,
@@ -178,34 +179,17 @@ __global__ void __launch_bounds__(kBlock) k_pcg_init(PcgArgs P, const double *rh
   block_partial(part, P.partials);
 }
 
-// Flat vector kernels: the leaf vectors of the Krylov iteration are
-// contiguous (device order) and zero on inactive cells, so x/r updates,
-// (r, z) and p = z + beta p are plain streams of 2-element vectors.
+// (r, z) over the leaf bricks (wave_loop grid)
 template <class V>
-struct Vec2;
-template <>
-struct Vec2<double> {
-  using T = double2;
-};
-template <>
-struct Vec2<float> {
-  using T = float2;
-};
-
-// (r, z) and beta = (r, z) / (r, z)_old (beta = 0 on the first call)
-template <class V>
-__global__ void __launch_bounds__(kBlock) k_pcg_rz(PcgArgs P, const double *r, const V *z,
-                                                   int64_t n2) {
+__global__ void __launch_bounds__(kBlock) k_pcg_rz(PcgArgs P, const double *r, const V *z) {
   if (P.S->done) return;
+  uint32_t m = threadIdx.x & (kWave - 1);
+  const __amdgpu_buffer_rsrc_t rr = make_rsrc(r, uint64_t(P.T.nlb) * 64 * sizeof(double));
+  const __amdgpu_buffer_rsrc_t zr = make_rsrc(z, uint64_t(P.T.nlb) * 64 * sizeof(V));
+  const WaveLoop W = wave_loop(P.T.nlb);
   double part = 0.0;
-  const double2 *r2 = reinterpret_cast<const double2 *>(r);
-  const typename Vec2<V>::T *z2 = reinterpret_cast<const typename Vec2<V>::T *>(z);
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n2;
-       i += int64_t(gridDim.x) * blockDim.x) {
-    double2 a = r2[i];
-    auto b = z2[i];
-    part += a.x * double(b.x) + a.y * double(b.y);
-  }
+  for (uint32_t b = W.first; b < W.end; b += W.step)
+    part += bload<double>(rr, m, b * 64u) * double(bload<V>(zr, m, b * 64u));
   block_partial(part, P.partials);
 }
 
@@ -360,6 +344,9 @@ __global__ void __launch_bounds__(1024) k_finish(PcgArgs P, int64_t n, int op, i
       else if (arg == 2) S->tr = tot;
       break;
   }
+  // the host polls the stop flag here instead of copying the scalars back
+  if (P.host_done) __hip_atomic_store(P.host_done, S->done, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // x += alpha p, r -= alpha Ap, ||r||^2 and the stop test
@@ -375,7 +362,6 @@ __global__ void __launch_bounds__(kBlock) k_pcg_update(PcgArgs P, double *x, dou
   double2 *r2 = reinterpret_cast<double2 *>(r);
   const double2 *p2 = reinterpret_cast<const double2 *>(p);
   const double2 *a2 = reinterpret_cast<const double2 *>(Ap);
-  typename Vec2<V>::T *l2 = reinterpret_cast<typename Vec2<V>::T *>(r_low);
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n2;
        i += int64_t(gridDim.x) * blockDim.x) {
     double2 xv = x2[i], rv = r2[i], pv = p2[i], av = a2[i];
@@ -386,10 +372,8 @@ __global__ void __launch_bounds__(kBlock) k_pcg_update(PcgArgs P, double *x, dou
     x2[i] = xv;
     r2[i] = rv;
     if (r_low) {
-      typename Vec2<V>::T lv;
-      lv.x = V(rv.x);
-      lv.y = V(rv.y);
-      l2[i] = lv;
+      r_low[2 * i] = V(rv.x);
+      r_low[2 * i + 1] = V(rv.y);
     }
     part += rv.x * rv.x + rv.y * rv.y;
   }
@@ -517,18 +501,20 @@ __global__ void __launch_bounds__(kBlock) k_residual_vec(PcgArgs P, const double
   }
 }
 
-// Streaming copy (measurement of the achievable HBM bandwidth): each thread
-// moves four 32-byte groups, all loads issued before the stores.
-__global__ void __launch_bounds__(256) k_stream_copy(const double4 *__restrict__ src,
-                                                     double4 *__restrict__ dst, int64_t n) {
-  int64_t i = (int64_t(blockIdx.x) * 4) * blockDim.x + threadIdx.x;
-  double4 v[4];
+// Streaming copy (measurement of the achievable HBM bandwidth): 16-byte
+// nontemporal accesses, each thread issuing its four loads before its four
+// stores.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) k_stream_copy(const f32x4 *__restrict__ src,
+                                                     f32x4 *__restrict__ dst, int64_t n) {
+  int64_t i = int64_t(blockIdx.x) * 1024 + threadIdx.x;
+  f32x4 v[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k)
-    if (i + k * blockDim.x < n) v[k] = src[i + k * blockDim.x];
+    if (i + k * 256 < n) v[k] = __builtin_nontemporal_load(src + i + k * 256);
 #pragma unroll
   for (int k = 0; k < 4; ++k)
-    if (i + k * blockDim.x < n) dst[i + k * blockDim.x] = v[k];
+    if (i + k * 256 < n) __builtin_nontemporal_store(v[k], dst + i + k * 256);
 }
 
 // ---------------------------------------------------------------------------
