@@ -255,6 +255,17 @@ def main():
             f"cycle {ms_c:.3f} ms = {by_c / ms_c / 1e6:.0f} GB/s; "
             f"streaming copy {by_cp / ms_cp / 1e6:.0f} GB/s; adjoint solve + gradient "
             f"{dt_adj * 1e3:.1f} ms ({ast['iters']} iterations)")
+    # the mu = 2 cycle (W-cycle) with the mixed hierarchy, outside the timed region
+    hw = mfmg.build_hierarchy(co, precision=mfmg.MIXED, mu=2)
+    mfmg.pcg_solve(hw, rhs_d, p, rtol=1e-10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, stw = mfmg.pcg_solve(hw, rhs_d, p, rtol=1e-10)
+    torch.cuda.synchronize()
+    dt_w = time.perf_counter() - t0
+    del hw
+    log(f"[bench] mixed W-cycle (mu=2): {dt_w * 1e3:.2f} ms/solve, {stw['iters']} iterations, "
+        f"true residual {stw['rel_resid_true']:.2e}")
     head = out["mixed"]
     traffic = measured_traffic("mixed", L)
     roof = {"bound": "hbm", "achieved": head["smooth_gbs"], "peak": HBM_PEAK_GBS,
@@ -299,7 +310,8 @@ def main():
                  "adjoint_iters": out["fp64"]["adjoint_iters"]},
         "mixed": {"iters": head["iters"], "rel_resid_true": head["rel_resid_true"],
                   "vcycle_gbs": head["cycle_gbs"], "vcycle_ms": head["cycle_ms"],
-                  "adjoint_ms": head["adjoint_ms"], "adjoint_iters": head["adjoint_iters"]},
+                  "adjoint_ms": head["adjoint_ms"], "adjoint_iters": head["adjoint_iters"],
+                  "wcycle_ms_per_solve": dt_w * 1e3, "wcycle_iters": stw["iters"]},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -193,6 +193,10 @@ typedef struct {
   int max_iter;   /* iteration cap (200)                                      */
   int null_space; /* -1 auto (on iff no Dirichlet wall), 0 off, 1 on: shift */
                   /* the residual to zero mean over active cells (Sec. 2.2)  */
+  int warm_start; /* 1: p holds an initial guess x0 on input (Algorithm 1   */
+                  /* from x0); the stop test becomes ||r_k|| <= rtol ||rhs||  */
+                  /* (equal to ||r_0|| for the zero start).  Forward solves */
+                  /* without the null-space shift only.  0: start from zero. */
 } mfmg_solve_params;
 
 typedef struct {
@@ -203,7 +207,8 @@ typedef struct {
   double seconds;         /* device time of the solve (HIP events)           */
 } mfmg_solve_stats;
 
-/* Solve A p = rhs (Algorithm 1, x0 = 0).  rhs, p: device, n_leaves doubles
+/* Solve A p = rhs (Algorithm 1 from x0 = 0, or from p when warm_start).
+ * rhs, p: device, n_leaves doubles
  * in canonical order; entries of inactive leaves are ignored on input and
  * set to 0 on output.  hist (host, may be NULL) receives max_iter + 1
  * relative residuals (the first iters + 1 are meaningful).

@@ -29,8 +29,13 @@ class BreakdownError(RuntimeError):
 
 
 def pcg(A, b, precond=None, rtol=1e-10, max_iter=200, null_space=False,
-        active=None, x_out=None):
-    """Returns (x, info) with info = dict(iters, hist, true, status)."""
+        active=None, x_out=None, x0=None):
+    """Returns (x, info) with info = dict(iters, hist, true, status).
+
+    x0 (optional) is an initial guess: the iteration starts from the residual
+    b - A x0, and the stop test and the history are taken relative to
+    ||b|| (which is ||r_0|| for the zero start), so a good guess stops
+    earlier at the same accuracy."""
     b = np.asarray(b, dtype=np.float64)
     n = len(b)
     if active is None:
@@ -44,12 +49,21 @@ def pcg(A, b, precond=None, rtol=1e-10, max_iter=200, null_space=False,
         return np.where(active, v - v[active].sum() / nact, 0.0)
 
     M = precond if precond is not None else (lambda r: r.copy())
-    x = np.zeros(n)
-    r = project(b.copy())
-    r0 = np.linalg.norm(r)
-    hist = [1.0 if r0 > 0 else 0.0]
+    if x0 is None:
+        x = np.zeros(n)
+        r = project(b.copy())
+        r0 = np.linalg.norm(r)
+        hist = [1.0 if r0 > 0 else 0.0]
+    else:
+        x = np.where(active, np.asarray(x0, dtype=np.float64), 0.0)
+        r = project(np.where(active, b - A @ x, 0.0))
+        r0 = np.linalg.norm(project(b.copy()))
+        hist = [np.linalg.norm(r) / r0 if r0 > 0 else 0.0]
     info = {"iters": 0, "hist": hist, "true": 0.0, "status": 0}
     if r0 == 0.0:
+        return x, info
+    if x0 is not None and np.linalg.norm(r) <= rtol * r0:
+        info["true"] = hist[0]
         return x, info
     z = np.where(active, M(r), 0.0)
     p = z.copy()

@@ -1022,7 +1022,8 @@ static hipGraphExec_t iteration_graph(mfmg_hierarchy *h, double *r, V *r_low, V 
 
 template <class V>
 static void pcg_iterate(mfmg_hierarchy *h, const double *rhs, double *r, V *r_low, V *z,
-                        const mfmg_solve_params *sp, bool null_space, hipStream_t s) {
+                        const mfmg_solve_params *sp, bool null_space, hipStream_t s,
+                        const double *x0) {
   PcgArgs P = pcg_args(h);
   unsigned G = grid_reduce(h->co->dt->nlb);
   Reduce R(h, s);
@@ -1032,6 +1033,15 @@ static void pcg_iterate(mfmg_hierarchy *h, const double *rhs, double *r, V *r_lo
   __atomic_store_n(h->host_done, 0, __ATOMIC_RELEASE);  // the stream is idle here
   R.init<V>(rhs, r, r_low, x, sp->rtol);
   if (null_space) R.shift_mean<V>(r, r_low, na, 0, sp->rtol);
+  if (x0) {
+    // r = rhs - A x0; the tolerance stays rtol ||rhs|| from the step above
+    hipLaunchKernelGGL(k_full, dim3(G), dim3(kBlock), 0, s, P, x0, h->Xf.p, 1);
+    hipLaunchKernelGGL(k_residual_vec, dim3(level_grid(h->co->dt->nlb)), dim3(kBlock), 0, s,
+                       P, rhs, (const double *)h->Xf.p, r);
+    hipLaunchKernelGGL(k_warm_start<V>, dim3(G), dim3(kBlock), 0, s, P, x0, x,
+                       (const double *)r, r_low);
+    R.finish(G, kFinWarm);
+  }
   Krylov<V> K(h, s);
   run_cycle(h, s, done);
   K.rz(r, z, 1);
@@ -1075,6 +1085,10 @@ extern "C" mfmg_status mfmg_pcg_solve(mfmg_hierarchy *h, const double *rhs, doub
   if (sp->null_space < -1 || sp->null_space > 1)
     return fail(MFMG_ERR_INVALID_ARG, "null_space must be -1, 0 or 1");
   bool ns = sp->null_space == 1 || (sp->null_space == -1 && !h->co->has_dirichlet);
+  if (sp->warm_start != 0 && sp->warm_start != 1)
+    return fail(MFMG_ERR_INVALID_ARG, "warm_start must be 0 or 1");
+  if (sp->warm_start && ns)
+    return fail(MFMG_ERR_INVALID_ARG, "warm start is not available with the null-space shift");
   hipStream_t s = (hipStream_t)stream;
   mfmg_status st = MFMG_OK;
   try {
@@ -1087,9 +1101,11 @@ extern "C" mfmg_status mfmg_pcg_solve(mfmg_hierarchy *h, const double *rhs, doub
     HIP_CHECK(hipEventCreate(&e1));
     HIP_CHECK(hipEventRecord(e0, s));
     if (h->prm.precision == MFMG_MIXED)
-      pcg_iterate<float>(h, rhs, h->r.p, h->B32.p, h->U32.p, sp, ns, s);
+      pcg_iterate<float>(h, rhs, h->r.p, h->B32.p, h->U32.p, sp, ns, s,
+                         sp->warm_start ? (const double *)p : nullptr);
     else
-      pcg_iterate<double>(h, rhs, h->B64.p, (double *)nullptr, h->U64.p, sp, ns, s);
+      pcg_iterate<double>(h, rhs, h->B64.p, (double *)nullptr, h->U64.p, sp, ns, s,
+                          sp->warm_start ? (const double *)p : nullptr);
     PcgArgs P = pcg_args(h);
     hipLaunchKernelGGL(k_to_canonical<double>, dim3(grid_for(h->co->dt->nlb)), dim3(kBlock), 0,
                        s, P, (const double *)h->x.p, p);
@@ -1173,6 +1189,7 @@ extern "C" mfmg_status mfmg_pcg_solve_adjoint(mfmg_hierarchy *h, const double *p
   if (sp->null_space < -1 || sp->null_space > 1)
     return fail(MFMG_ERR_INVALID_ARG, "null_space must be -1, 0 or 1");
   bool ns = sp->null_space == 1 || (sp->null_space == -1 && !h->co->has_dirichlet);
+  if (sp->warm_start) return fail(MFMG_ERR_INVALID_ARG, "the adjoint solve starts from zero");
   hipStream_t s = (hipStream_t)stream;
   const Topology &T = h->co->tree->topo;
   const DeviceTopology &D = *h->co->dt;

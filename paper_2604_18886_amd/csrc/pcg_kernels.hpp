@@ -179,6 +179,23 @@ __global__ void __launch_bounds__(kBlock) k_pcg_init(PcgArgs P, const double *rh
   block_partial(part, P.partials);
 }
 
+// Warm start (Algorithm 1 from an initial guess): r already holds rhs - A x0;
+// x = x0 (canonical input) on active cells, the FP32 copy of r, ||r||^2.
+template <class V>
+__global__ void __launch_bounds__(kBlock) k_warm_start(PcgArgs P, const double *x0, double *x,
+                                                       const double *r, V *r_low) {
+  double part = 0.0;
+  LEAF_LOOP(P) {
+    const BrickMeta M = P.T.meta[b];
+    bool act = (act_mask(M) >> m) & 1ull;
+    x[b * 64u + m] = act ? x0[uint32_t(P.canon[b]) * 64u + m] : 0.0;
+    double v = r[b * 64u + m];
+    if (r_low) r_low[b * 64u + m] = V(v);
+    part += v * v;
+  }
+  block_partial(part, P.partials);
+}
+
 // (r, z) over the leaf bricks (wave_loop grid)
 template <class V>
 __global__ void __launch_bounds__(kBlock) k_pcg_rz(PcgArgs P, const double *r, const V *z) {
@@ -263,6 +280,7 @@ enum FinishOp : int {
   kFinTrue = 4,   // ||rhs - A x||^2
   kFinSum = 5,    // sum over active cells (null-space mean)
   kFinShift = 6,  // ||v||^2 after the mean shift, arg = mode of k_shift_mean
+  kFinWarm = 7,   // ||rhs - A x0||^2 of a warm start (tolerance kept from ||rhs||)
 };
 
 __device__ __forceinline__ void finish_iteration(const PcgArgs &P, double tot) {
@@ -342,6 +360,16 @@ __global__ void __launch_bounds__(1024) k_finish(PcgArgs P, int64_t n, int op, i
       if (arg == 0) finish_initial(P, tot, rtol);
       else if (arg == 1) finish_iteration(P, tot);
       else if (arg == 2) S->tr = tot;
+      break;
+    case kFinWarm:
+      S->rr = tot;
+      P.hist[0] = S->rr0 > 0.0 ? sqrt(tot / S->rr0) : 0.0;
+      if (!(tot < INFINITY)) {
+        S->status = -5;
+        S->done = 1;
+      } else if (tot <= S->tol2) {
+        S->done = 1;
+      }
       break;
   }
   // the host polls the stop flag here instead of copying the scalars back

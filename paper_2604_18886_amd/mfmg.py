@@ -57,7 +57,7 @@ class _MGParams(ctypes.Structure):
 
 class _SolveParams(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int),
-                ("null_space", ctypes.c_int)]
+                ("null_space", ctypes.c_int), ("warm_start", ctypes.c_int)]
 
 
 class SolveStats(ctypes.Structure):
@@ -291,12 +291,17 @@ def build_hierarchy(coeffs, nu_pre=2, nu_post=2, nu_coarse=10, mu=1, coarsest_le
 
 
 # ----------------------------------------------------------------------- solve
-def pcg_solve(h, rhs, p=None, rtol=1e-10, max_iter=200, null_space=-1, history=False):
-    """Solve A p = rhs; returns (p, stats dict[, residual history])."""
+def pcg_solve(h, rhs, p=None, rtol=1e-10, max_iter=200, null_space=-1, history=False,
+              x0=None):
+    """Solve A p = rhs; returns (p, stats dict[, residual history]).  With x0
+    (device tensor) the iteration starts from that guess and stops at
+    ||r|| <= rtol ||rhs||."""
     torch = _torch()
     if p is None:
         p = torch.empty_like(rhs)
-    sp = _SolveParams(float(rtol), int(max_iter), int(null_space))
+    if x0 is not None:
+        p.copy_(x0)
+    sp = _SolveParams(float(rtol), int(max_iter), int(null_space), int(x0 is not None))
     st = SolveStats()
     hist = np.zeros(max_iter + 1) if history else None
     status = _lib.mfmg_pcg_solve(h._h, _ptr(rhs), _ptr(p), ctypes.byref(sp), _stream(),
@@ -314,7 +319,7 @@ def pcg_solve_adjoint(h, p, dL_dp, rtol=1e-10, max_iter=200, null_space=-1):
     torch = _torch()
     lam = torch.empty_like(dL_dp)
     g = torch.empty(h.coeffs.tree.n_faces, dtype=torch.float64, device=dL_dp.device)
-    sp = _SolveParams(float(rtol), int(max_iter), int(null_space))
+    sp = _SolveParams(float(rtol), int(max_iter), int(null_space), 0)
     st = SolveStats()
     status = _lib.mfmg_pcg_solve_adjoint(h._h, _ptr(p), _ptr(dL_dp), _ptr(lam), _ptr(g),
                                          ctypes.byref(sp), _stream(), ctypes.byref(st))

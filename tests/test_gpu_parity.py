@@ -165,3 +165,34 @@ def test_w_cycle_matches_oracle(mu):
     assert st["status"] == 0
     assert abs(st["iters"] - info10["iters"]) <= 1
     assert rel(p.cpu().numpy(), x) <= 1e-9
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_warm_start_matches_oracle(precision):
+    """Algorithm 1 from an initial guess (the previous solution perturbed):
+    same stop test relative to ||rhs||, same iterations as the oracle's
+    warm start, and a guess that already meets the tolerance takes none."""
+    import problems
+    from gpu_fixtures import Case
+    from oracle import krylov as K
+    from paper_2604_18886_amd import mfmg
+    case = Case(3, problems.config_spec(3, 5, 7))
+    act = case.disc.active
+    xs, _ = case.oracle_solve(1e-13)
+    rng = np.random.default_rng(45)
+    x0 = np.where(act, xs * (1 + 1e-3 * rng.standard_normal(case.T.n)), 0.0)
+    h = case.gpu_hierarchy(precision=precision)
+    p, st, hist = mfmg.pcg_solve(h, case.device(case.rhs), rtol=1e-10, history=True,
+                                 x0=case.device(x0))
+    xw, iw = K.pcg(case.disc.A, case.rhs, case.hier.vcycle, 1e-10, 400, active=act, x0=x0)
+    p = p.cpu().numpy()
+    print(f"  precision={precision} warm: gpu iters={st['iters']} oracle={iw['iters']} "
+          f"true={st['rel_resid_true']:.2e} err={rel(p, xs):.2e}", flush=True)
+    assert st["status"] == 0 and st["rel_resid_true"] <= 1.5e-10
+    assert rel(p, xs) <= 1e-9
+    if precision == 0:
+        assert abs(st["iters"] - iw["iters"]) <= 1
+        assert np.allclose(hist[: len(iw["hist"])], iw["hist"][: len(hist)], rtol=1e-6,
+                           atol=1e-14)
+    _, st0 = mfmg.pcg_solve(h, case.device(case.rhs), rtol=1e-10, x0=case.device(xs))
+    assert st0["iters"] == 0 and st0["status"] == 0

@@ -11,7 +11,7 @@ from oracle import discretize as D
 from oracle import krylov as K
 from oracle import octree as O
 
-from oracle_fixtures import disc_for, half_tree, hierarchy
+from oracle_fixtures import config_problem, disc_for, half_tree, hierarchy
 
 
 def test_identity_preconditioner_is_plain_cg():
@@ -86,3 +86,23 @@ def test_zero_rhs_and_max_iter():
     rhs = problems.rhs_manufactured(1, d.tree.level, d.tree.ijk)
     x, info = K.pcg(d.A, rhs, hierarchy(d).vcycle, 1e-10, 1)
     assert info["iters"] == 1 and info["status"] == 1
+
+
+def test_warm_start_is_a_shifted_cold_start():
+    """Algorithm 1 from x0 on b takes the same steps as the zero start on
+    b - A x0 (with the stop threshold carried over): x = x0 + x'."""
+    T, d, beta, rhs = config_problem(3, min_level=4, max_level=6)
+    H = hierarchy(d)
+    xs, _ = K.pcg(d.A, rhs, H.vcycle, 1e-12, 300, active=d.active)
+    rng = np.random.default_rng(44)
+    x0 = np.where(d.active, xs * (1 + 1e-3 * rng.standard_normal(T.n)), 0.0)
+    xw, iw = K.pcg(d.A, rhs, H.vcycle, 1e-10, 300, active=d.active, x0=x0)
+    b2 = np.where(d.active, rhs - d.A @ x0, 0.0)
+    scale = np.linalg.norm(np.where(d.active, rhs, 0.0)) / np.linalg.norm(b2)
+    xc, ic = K.pcg(d.A, b2, H.vcycle, 1e-10 * scale, 300, active=d.active)
+    assert iw["iters"] == ic["iters"] and iw["iters"] < 10
+    assert np.allclose(iw["hist"], np.array(ic["hist"]) / scale, rtol=1e-9, atol=0)
+    assert np.linalg.norm(xw - (x0 + xc)) <= 1e-12 * np.linalg.norm(xw)
+    # a guess that already meets the tolerance takes no iteration
+    _, i0 = K.pcg(d.A, rhs, H.vcycle, 1e-10, 300, active=d.active, x0=xs)
+    assert i0["iters"] == 0 and i0["status"] == 0
