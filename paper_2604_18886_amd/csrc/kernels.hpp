@@ -678,6 +678,7 @@ struct LevelArgsT {
   V *YS;     // (nb - nlb) * 64
   Range R;
   V bscale;  // beta_mg / alpha
+  const int *done;  // skip when the solve has stopped (may be null)
 };
 
 // Transposed level operator at one cell, applied to W:
@@ -734,6 +735,7 @@ __device__ __forceinline__ V level_AuT(const Coefs<V, CL, CI> &cf, const V *__re
 // colour (0 elsewhere), Y += w, W = w.
 template <class V, class CL, class CI>
 __global__ void __launch_bounds__(kBlock) k_T_sweep_w(LevelArgsT<V, CL, CI> A, int colour) {
+  if (A.done && *A.done) return;
   uint32_t i = blockIdx.x * kWavesPerBlock + wave_id();
   int m = threadIdx.x & (kWave - 1);
   if (i >= A.R.n()) return;
@@ -750,6 +752,7 @@ __global__ void __launch_bounds__(kBlock) k_T_sweep_w(LevelArgsT<V, CL, CI> A, i
 // RHO -= A^T W on the bricks of the range.
 template <class V, class CL, class CI>
 __global__ void __launch_bounds__(kBlock) k_T_apply(LevelArgsT<V, CL, CI> A) {
+  if (A.done && *A.done) return;
   uint32_t i = blockIdx.x * kWavesPerBlock + wave_id();
   int m = threadIdx.x & (kWave - 1);
   if (i >= A.R.n()) return;
@@ -766,6 +769,7 @@ __global__ void __launch_bounds__(kBlock) k_T_apply(LevelArgsT<V, CL, CI> A) {
 // to J of (k_f / 2) W_f (the fine cells are children of J's inner neighbour).
 template <class V, class CL, class CI>
 __global__ void __launch_bounds__(kBlock) k_T_coupling(LevelArgsT<V, CL, CI> A) {
+  if (A.done && *A.done) return;
   uint32_t i = blockIdx.x * kWavesPerBlock + wave_id();
   int m = threadIdx.x & (kWave - 1);
   if (i >= A.R.n()) return;
@@ -796,6 +800,7 @@ __global__ void __launch_bounds__(kBlock) k_T_coupling(LevelArgsT<V, CL, CI> A) 
 // parents, RHO_P += sum_active_children RHO, SBAR_P = -(that sum).
 template <class V, class CL, class CI>
 __global__ void __launch_bounds__(kBlock) k_T_restrict(LevelArgsT<V, CL, CI> A) {
+  if (A.done && *A.done) return;
   uint32_t i = blockIdx.x * kWavesPerBlock + wave_id();
   int m = threadIdx.x & (kWave - 1);
   if (i >= A.R.n()) return;
@@ -816,6 +821,7 @@ __global__ void __launch_bounds__(kBlock) k_T_restrict(LevelArgsT<V, CL, CI> A) 
 // bricks set W = 0.
 template <class V, class CL, class CI>
 __global__ void __launch_bounds__(kBlock) k_T_coarse(LevelArgsT<V, CL, CI> A) {
+  if (A.done && *A.done) return;
   uint32_t i = blockIdx.x * kWavesPerBlock + wave_id();
   int m = threadIdx.x & (kWave - 1);
   if (i >= A.R.n()) return;
@@ -839,6 +845,7 @@ __global__ void __launch_bounds__(kBlock) k_T_coarse(LevelArgsT<V, CL, CI> A) {
 // leaves); inner cells SBAR += t, leaf cells RHO += t.
 template <class V, class CL, class CI>
 __global__ void __launch_bounds__(kBlock) k_T_fas(LevelArgsT<V, CL, CI> A) {
+  if (A.done && *A.done) return;
   uint32_t i = blockIdx.x * kWavesPerBlock + wave_id();
   int m = threadIdx.x & (kWave - 1);
   if (i >= A.R.n()) return;
@@ -857,6 +864,7 @@ __global__ void __launch_bounds__(kBlock) k_T_fas(LevelArgsT<V, CL, CI> A) {
 // tbar = (beta_mg / alpha) YS_P, Y += tbar, W = tbar (0 on inactive cells).
 template <class V, class CL, class CI>
 __global__ void __launch_bounds__(kBlock) k_T_prolong(LevelArgsT<V, CL, CI> A) {
+  if (A.done && *A.done) return;
   uint32_t i = blockIdx.x * kWavesPerBlock + wave_id();
   int m = threadIdx.x & (kWave - 1);
   if (i >= A.R.n()) return;
@@ -881,6 +889,7 @@ __global__ void __launch_bounds__(kBlock) k_T_prolong(LevelArgsT<V, CL, CI> A) {
 // order, each as w = RHO / c on the colour, Y += w, RHO -= A^T w.
 template <class V, class CL, class CI>
 __global__ void __launch_bounds__(1024) k_T_coarsest(LevelArgsT<V, CL, CI> A, int nu) {
+  if (A.done && *A.done) return;
   uint32_t w = wave_id();
   uint32_t nw = blockDim.x / kWave;
   int m = threadIdx.x & (kWave - 1);

@@ -699,6 +699,7 @@ struct CycleT {
   const CL *tc;
   V *RHO, *Y, *W, *SBAR, *YS;
   hipStream_t s;
+  const int *done;
 
   V iscale(int l) const {
     return std::is_same<CI, __half>::value ? V(std::ldexp(1.0, -l)) : V(1);
@@ -723,6 +724,7 @@ struct CycleT {
       A.R.inner_lo = 0;
     }
     A.bscale = V(h->prm.beta_mg / h->prm.alpha);
+    A.done = done;
     return A;
   }
   void launch_apply(int l) const {
@@ -790,18 +792,20 @@ void alloc_transpose(const mfmg_hierarchy *hc, DevBuf<V> (&T)[5]) {
 
 // z = M^T r: r, z FP64 leaf vectors in device order; returns the z buffer
 // (the Y leaf part, of the cycle's value type)
-void run_cycle_T(mfmg_hierarchy *h, const double *r, hipStream_t s) {
+void run_cycle_T(mfmg_hierarchy *h, const double *r, hipStream_t s,
+                 const int *done = nullptr) {
   if (h->prm.precision == MFMG_MIXED) {
     alloc_transpose(h, h->T32);
     CycleT<float, float, __half> c{h, h->coef32.p, h->coef16.p, h->tc32.p, h->T32[0].p,
-                                   h->T32[1].p, h->T32[2].p, h->T32[3].p, h->T32[4].p, s};
+                                   h->T32[1].p, h->T32[2].p, h->T32[3].p, h->T32[4].p, s,
+                                   done};
     c.run(r);
   } else {
     alloc_transpose(h, h->T64);
     CycleT<double, double, double> c{h, h->coef64.p,
                                      h->coef64.p + int64_t(h->co->dt->nlb) * 256,
                                      h->co->tc.p, h->T64[0].p, h->T64[1].p, h->T64[2].p,
-                                     h->T64[3].p, h->T64[4].p, s};
+                                     h->T64[3].p, h->T64[4].p, s, done};
     c.run(r);
   }
 }
@@ -1149,25 +1153,27 @@ static void pcg_adjoint_iterate(mfmg_hierarchy *h, const double *g, V *z,
   Reduce R(h, s);
   double na = std::max(1.0, h->n_active);
   double *x = h->x.p, *r = h->rA.p;
+  const int *done = &h->S.p->done;
+  __atomic_store_n(h->host_done, 0, __ATOMIC_RELEASE);  // the stream is idle here
   R.init<V>(g, r, (V *)nullptr, x, sp->rtol);
   if (null_space) R.shift_mean<V>(r, (V *)nullptr, na, 0, sp->rtol);
-  HIP_CHECK(hipMemcpyAsync(h->hostS, h->S.p, sizeof(Scalars), hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipStreamSynchronize(s));
-  if (!h->hostS->done) {
-    Krylov<V> K(h, s);
-    run_cycle_T(h, r, s);
-    K.rz(r, z, 1);
-    K.pupdate(z, 1);
-    for (int it = 0; it < sp->max_iter; ++it) {
-      K.Ap(true);
-      K.update(x, r, (V *)nullptr, int(null_space));
-      if (null_space) R.shift_mean<V>(r, (V *)nullptr, na, 1, sp->rtol);
-      HIP_CHECK(hipMemcpyAsync(h->hostS, h->S.p, sizeof(Scalars), hipMemcpyDeviceToHost, s));
-      HIP_CHECK(hipStreamSynchronize(s));
-      if (h->hostS->done) break;
-      run_cycle_T(h, r, s);
-      K.rz(r, z, 0);
-      K.pupdate(z, 0);
+  Krylov<V> K(h, s);
+  run_cycle_T(h, r, s, done);
+  K.rz(r, z, 1);
+  K.pupdate(z, 1);
+  for (int it = 0; it < sp->max_iter; ++it) {
+    K.Ap(true);
+    K.update(x, r, (V *)nullptr, int(null_space));
+    if (null_space) R.shift_mean<V>(r, (V *)nullptr, na, 1, sp->rtol);
+    run_cycle_T(h, r, s, done);
+    K.rz(r, z, 0);
+    K.pupdate(z, 0);
+    // stop flag of iteration it read after iteration it + 1 is queued (as in
+    // the forward solve); kernels queued after the stop return at once
+    HIP_CHECK(hipEventRecord(h->iter_ev[it & 1], s));
+    if (it > 0) {
+      HIP_CHECK(hipEventSynchronize(h->iter_ev[(it - 1) & 1]));
+      if (__atomic_load_n(h->host_done, __ATOMIC_ACQUIRE)) break;
     }
   }
   if (null_space) R.shift_mean<double>(x, (double *)nullptr, na, 3, 0.0);
@@ -1248,9 +1254,16 @@ extern "C" mfmg_status mfmg_pcg_solve_adjoint(mfmg_hierarchy *h, const double *p
     unsigned G = grid_for(D.nlb);
     hipLaunchKernelGGL(k_to_canonical<double>, dim3(G), dim3(kBlock), 0, s, P,
                        (const double *)h->x.p, lambda);
-    // true residual of the adjoint system: canonical A^T lambda vs dL/dp
-    hipLaunchKernelGGL(k_to_canonical<double>, dim3(G), dim3(kBlock), 0, s, P,
-                       (const double *)h->Ap.p, h->Xf.p);
+    // true residual of the adjoint system, ||dL/dp - A^T lambda|| (shifted
+    // to zero mean with the null space), on the device
+    {
+      Reduce R(h, s);
+      hipLaunchKernelGGL(k_resid_T, dim3(R.G), dim3(kBlock), 0, s, P, dL_dp,
+                         (const double *)h->Ap.p, h->Xf.p);
+      R.finish(R.G, kFinTrue);
+      if (ns) R.shift_mean<double>(h->Xf.p, (double *)nullptr, std::max(1.0, h->n_active), 2,
+                                   0.0);
+    }
     GradArgs A;
     A.owner = h->f_owner.p;
     A.other = h->f_other.p;
@@ -1272,23 +1285,6 @@ extern "C" mfmg_status mfmg_pcg_solve_adjoint(mfmg_hierarchy *h, const double *p
     HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    // ||dL/dp - A^T lambda|| on the host from the canonical vectors
-    int64_t N = int64_t(D.nlb) * 64;
-    std::vector<double> gt(N), at(N);
-    std::vector<uint64_t> am(D.nlb);
-    HIP_CHECK(hipMemcpy(gt.data(), dL_dp, N * sizeof(double), hipMemcpyDeviceToHost));
-    HIP_CHECK(hipMemcpy(at.data(), h->Xf.p, N * sizeof(double), hipMemcpyDeviceToHost));
-    HIP_CHECK(hipMemcpy(am.data(), h->canon_act.p, D.nlb * sizeof(uint64_t),
-                        hipMemcpyDeviceToHost));
-    double tr = 0.0, sum = 0.0, na = 0.0;
-    for (int64_t i = 0; i < N; ++i)
-      if ((am[i >> 6] >> (i & 63)) & 1ull) {
-        double t = gt[i] - at[i];
-        tr += t * t;
-        sum += t;
-        na += 1.0;
-      }
-    if (ns && na > 0) tr -= sum * sum / na;
     const Scalars &S = *h->hostS;
     if (S.status == -5)
       st = MFMG_ERR_BREAKDOWN;
@@ -1298,7 +1294,7 @@ extern "C" mfmg_status mfmg_pcg_solve_adjoint(mfmg_hierarchy *h, const double *p
       stats->iters = S.iters;
       stats->status = st;
       stats->rel_resid_recur = S.rr0 > 0.0 ? std::sqrt(S.rr / S.rr0) : 0.0;
-      stats->rel_resid_true = S.rr0 > 0.0 ? std::sqrt(std::max(tr, 0.0) / S.rr0) : 0.0;
+      stats->rel_resid_true = S.rr0 > 0.0 ? std::sqrt(S.tr / S.rr0) : 0.0;
       stats->seconds = ms * 1e-3;
     }
   } catch (const HipError &e) {

@@ -465,6 +465,21 @@ __global__ void __launch_bounds__(kBlock) k_true_resid(PcgArgs P, const double *
   block_partial(part, P.partials);
 }
 
+// t = g - y on active cells (g canonical, y and t device order) and ||t||^2
+// (true residual of the adjoint system with y = A^T lambda)
+__global__ void __launch_bounds__(kBlock) k_resid_T(PcgArgs P, const double *g, const double *y,
+                                                    double *t) {
+  double part = 0.0;
+  LEAF_LOOP(P) {
+    const BrickMeta M = P.T.meta[b];
+    bool act = (act_mask(M) >> m) & 1ull;
+    double v = act ? g[uint32_t(P.canon[b]) * 64u + m] - y[b * 64u + m] : 0.0;
+    t[b * 64u + m] = v;
+    part += v * v;
+  }
+  block_partial(part, P.partials);
+}
+
 // device-order leaf vector of type V -> canonical FP64 (inactive cells 0)
 template <class V>
 __global__ void __launch_bounds__(kBlock) k_to_canonical(PcgArgs P, const V *src, double *dst) {
