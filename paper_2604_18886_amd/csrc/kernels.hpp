@@ -459,28 +459,40 @@ __device__ __forceinline__ T bload_bytes(__amdgpu_buffer_rsrc_t r, uint32_t voff
 // the only branch is a scalar one around the T-junction ghosts.  diag
 // returns c_m as the sum of the six face coefficients (see k_plus_faces),
 // so the diagonal is not streamed from memory.
-template <class V, class CL, class CI>
-__device__ __forceinline__ V stencil_sum(const LevelView<V, CL, CI> &X, const LaneC<V, CL> &L,
-                                         uint32_t b, const BrickMeta &M, V u, V k0, V k1,
-                                         V k2, V &diag) {
-  V v[6], k[6];
+// Values across the six faces of the lane's cell and their coefficients:
+// v[d] the same-level neighbour's entry of the vector in buffer x (0 at a
+// wall or T-face, where the load is out of range), k[d] the face
+// coefficient (own k_a on the minus side, the neighbour's on the plus side).
+template <class V, class CL>
+__device__ __forceinline__ void face_values(__amdgpu_buffer_rsrc_t x, __amdgpu_buffer_rsrc_t pf,
+                                            const LaneC<V, CL> &L, uint32_t b,
+                                            const BrickMeta &M, V u, V k0, V k1, V k2, V (&v)[6],
+                                            V (&k)[6]) {
 #pragma unroll
   for (int d = 0; d < 6; ++d) {
     int a = d >> 1;
     V kown = a == 0 ? k0 : (a == 1 ? k1 : k2);
     int32_t n = M.nbr[d];
     uint32_t sb = n >= 0 ? uint32_t(n) * uint32_t(64 * sizeof(V)) : kOutOfRange;
-    V vl = bload_bytes<V>(X.u, L.poff[d] + sb, 0);
+    V vl = bload_bytes<V>(x, L.poff[d] + sb, 0);
     V vs = shfl(u, L.p[d]);
     v[d] = L.out[d] ? vl : vs;
     if (d & 1) {
-      V kl = V(bload_bytes<CL>(X.pf, L.foff[a], b * uint32_t(48 * sizeof(CL))));
+      V kl = V(bload_bytes<CL>(pf, L.foff[a], b * uint32_t(48 * sizeof(CL))));
       V ks = shfl(kown, L.p[d]);
       k[d] = L.out[d] ? kl : ks;
     } else {
       k[d] = kown;
     }
   }
+}
+
+template <class V, class CL, class CI>
+__device__ __forceinline__ V stencil_sum(const LevelView<V, CL, CI> &X, const LaneC<V, CL> &L,
+                                         uint32_t b, const BrickMeta &M, V u, V k0, V k1,
+                                         V k2, V &diag) {
+  V v[6], k[6];
+  face_values(X.u, X.pf, L, b, M, u, k0, k1, k2, v, k);
   if (M.flags & kFlagT) {
     uint64_t amask = act_mask(M);
     bool act = (amask >> L.m) & 1ull;
@@ -679,51 +691,68 @@ struct LevelArgsT {
   Range R;
   V bscale;  // beta_mg / alpha
   const int *done;  // skip when the solve has stopped (may be null)
+  const CL *pf;     // plus-face coefficients (as LevelArgs::pf)
 };
 
-// Transposed level operator at one cell, applied to W:
-//   (c_m - sum_{T faces of m} k) W_m - sum_{other faces} k W_nbr
-//   + (1 / n_active siblings) sum over the sibling group's T-faces (k_i/2) W_i
-// (the coupling to the coarser level, B^T, is applied by k_T_coupling).
+// Buffer view of the transposed cycle's arrays on one level.
 template <class V, class CL, class CI>
-__device__ __forceinline__ V level_AuT(const Coefs<V, CL, CI> &cf, const V *__restrict__ W,
-                                       const BrickMeta &M, int m, V w, V c, V k0, V k1, V k2) {
+struct LevelViewT {
+  LevelView<V, CL, CI> c;  // coefficients and plus faces (u = W)
+  __amdgpu_buffer_rsrc_t rho, y, w, sbar, ys;
+};
+
+template <class V, class CL, class CI>
+__device__ __forceinline__ LevelViewT<V, CL, CI> level_view_T(const LevelArgsT<V, CL, CI> &A) {
+  LevelViewT<V, CL, CI> X;
+  uint64_t nb = A.T.nb, nlb = A.T.nlb;
+  X.rho = make_rsrc(A.RHO, nb * 64 * sizeof(V));
+  X.y = make_rsrc(A.Y, nb * 64 * sizeof(V));
+  X.w = make_rsrc(A.W, nb * 64 * sizeof(V));
+  X.sbar = make_rsrc(A.SBAR, (nb - nlb) * 64 * sizeof(V));
+  X.ys = make_rsrc(A.YS, (nb - nlb) * 64 * sizeof(V));
+  X.c.u = X.w;
+  X.c.b = X.w;
+  X.c.us = X.w;
+  X.c.cl = make_rsrc(A.cf.leaf, nlb * 256 * sizeof(CL));
+  X.c.ci = make_rsrc(A.cf.inner, (nb - nlb) * 256 * sizeof(CI));
+  X.c.pf = make_rsrc(A.pf, nb * 48 * sizeof(CL));
+  X.c.meta = A.T.meta;
+  X.c.nlb = A.T.nlb;
+  X.c.iscale = A.cf.iscale;
+  return X;
+}
+
+// Transposed level operator at the lane's cell, applied to W (w its own
+// entry):
+//   (c_m - sum_{T faces of m} k) w_m - sum_{other faces} k W_nbr
+//   + (1 / n_active siblings) sum over the sibling group's T-faces (k_i/2) w_i
+// (the coupling to the coarser level, B^T, is applied by k_T_coupling).  The
+// loads across T-faces are out of range, so those faces drop out of the
+// neighbour sum by themselves.
+template <bool INNER, class V, class CL, class CI>
+__device__ __forceinline__ V level_AuT(const LevelViewT<V, CL, CI> &X, const LaneC<V, CL> &L,
+                                       uint32_t b, const BrickMeta &M, V w) {
+  V k0 = own_coef<INNER>(X.c, b, 1, L.m);
+  V k1 = own_coef<INNER>(X.c, b, 2, L.m);
+  V k2 = own_coef<INNER>(X.c, b, 3, L.m);
   V v[6], k[6];
-#pragma unroll
-  for (int d = 0; d < 6; ++d) {
-    int a = d >> 1;
-    int p = dev_partner(m, d);
-    V kown = a == 0 ? k0 : (a == 1 ? k1 : k2);
-    v[d] = shfl(w, p);
-    k[d] = (d & 1) ? shfl(kown, p) : kown;
-  }
-#pragma unroll
-  for (int d = 0; d < 6; ++d) {
-    int p = dev_partner(m, d);
-    if (dev_outside(m, d) && M.nbr[d] >= 0) {
-      v[d] = W[uint32_t(M.nbr[d]) * 64u + p];
-      if (d & 1) k[d] = cf.get(uint32_t(M.nbr[d]), 1 + (d >> 1), p);
-    }
-  }
-#pragma unroll
-  for (int d = 0; d < 6; ++d)
-    if (dev_outside(m, d) && ((M.flags >> (16 + d)) & 1u)) v[d] = V(0);
+  face_values(X.w, X.c.pf, L, b, M, w, k0, k1, k2, v, k);
+  V c = ((k[0] + k[1]) + (k[2] + k[3])) + (k[4] + k[5]);
   uint64_t amask = act_mask(M);
-  bool act = (amask >> m) & 1ull;
+  bool act = (amask >> L.m) & 1ull;
   V acc = c * w;
   if (M.flags & kFlagT) {
     V tpart = V(0);
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
-      if (((M.flags >> d) & 1u) && dev_outside(m, d)) {
-        V kt = (d & 1) ? cf.tplus(M.tplus, d >> 1, dev_face_index(m, d >> 1)) : k[d];
+      if ((M.flags >> d) & 1u) {
+        V kt = L.out[d] ? k[d] : V(0);
         acc -= kt * w;
         tpart += kt * V(0.5) * w;
-        k[d] = V(0);
       }
     }
     V Ssum = group8_sum(tpart);
-    int cnt = __popcll((amask >> (m & 56)) & 0xffull);
+    int cnt = __popcll((amask >> (L.m & 56u)) & 0xffull);
     if (act && cnt) acc += Ssum / V(cnt);
   }
 #pragma unroll
@@ -731,37 +760,54 @@ __device__ __forceinline__ V level_AuT(const Coefs<V, CL, CI> &cf, const V *__re
   return act ? acc : V(0);
 }
 
-// First half of a transposed half-sweep: w = RHO / c on the cells of the
-// colour (0 elsewhere), Y += w, W = w.
+// First half of a transposed half-sweep: W = RHO / c on the active cells of
+// the colour, 0 elsewhere.
+template <bool INNER, class V, class CL, class CI>
+__device__ __forceinline__ void sweep_w_brick(const LevelViewT<V, CL, CI> &X,
+                                              const LaneC<V, CL> &L, uint32_t b, int colour) {
+  const BrickMeta M = load_meta(X.c.meta, b);
+  bool act = (act_mask(M) >> L.m) & 1ull;
+  V x = V(0);
+  if (act && L.colour == colour)
+    x = div_by(bload<V>(X.rho, L.m, b * 64u), own_coef<INNER>(X.c, b, 0, L.m));
+  bstore<V>(X.w, L.m, b * 64u, x);
+}
+
 template <class V, class CL, class CI>
 __global__ void __launch_bounds__(kBlock) k_T_sweep_w(LevelArgsT<V, CL, CI> A, int colour) {
   if (A.done && *A.done) return;
-  uint32_t i = blockIdx.x * kWavesPerBlock + wave_id();
-  int m = threadIdx.x & (kWave - 1);
-  if (i >= A.R.n()) return;
-  uint32_t b = A.R.brick(i);
-  const BrickMeta M = A.T.meta[b];
-  bool act = (act_mask(M) >> m) & 1ull;
-  int col = (dev_cx(m) + dev_cy(m) + dev_cz(m)) & 1;
-  V w = V(0);
-  if (act && col == colour) w = div_by(A.RHO[b * 64u + m], A.cf.get(b, 0, m));
-  A.W[b * 64u + m] = w;
-  if (w != V(0)) A.Y[b * 64u + m] += w;
+  const LaneC<V, CL> L = lane_consts<V, CL>();
+  const LevelViewT<V, CL, CI> X = level_view_T(A);
+  const WaveLoop W = wave_loop(A.R.n());
+  for (uint32_t i = W.first; i < W.end; i += W.step) {
+    if (i < A.R.n_leaf) sweep_w_brick<false>(X, L, A.R.leaf_lo + i, colour);
+    else sweep_w_brick<true>(X, L, A.R.inner_lo + (i - A.R.n_leaf), colour);
+  }
 }
 
-// RHO -= A^T W on the bricks of the range.
+// RHO -= A^T W on the bricks of the range; with colour >= 0 (a transposed
+// half-sweep) also Y += W on that colour's cells (W is zero elsewhere).
+template <bool INNER, class V, class CL, class CI>
+__device__ __forceinline__ void apply_T_brick(const LevelViewT<V, CL, CI> &X,
+                                              const LaneC<V, CL> &L, uint32_t b, int colour) {
+  const BrickMeta M = load_meta(X.c.meta, b);
+  V w = bload<V>(X.w, L.m, b * 64u);
+  V t = level_AuT<INNER>(X, L, b, M, w);
+  V rho = bload<V>(X.rho, L.m, b * 64u);
+  bstore<V>(X.rho, L.m, b * 64u, rho - t);
+  if (L.colour == colour) bstore<V>(X.y, L.m, b * 64u, bload<V>(X.y, L.m, b * 64u) + w);
+}
+
 template <class V, class CL, class CI>
-__global__ void __launch_bounds__(kBlock) k_T_apply(LevelArgsT<V, CL, CI> A) {
+__global__ void __launch_bounds__(kBlock) k_T_apply(LevelArgsT<V, CL, CI> A, int colour) {
   if (A.done && *A.done) return;
-  uint32_t i = blockIdx.x * kWavesPerBlock + wave_id();
-  int m = threadIdx.x & (kWave - 1);
-  if (i >= A.R.n()) return;
-  uint32_t b = A.R.brick(i);
-  const BrickMeta M = A.T.meta[b];
-  V c = A.cf.get(b, 0, m), k0 = A.cf.get(b, 1, m), k1 = A.cf.get(b, 2, m),
-    k2 = A.cf.get(b, 3, m);
-  V t = level_AuT(A.cf, A.W, M, m, A.W[b * 64u + m], c, k0, k1, k2);
-  A.RHO[b * 64u + m] -= t;
+  const LaneC<V, CL> L = lane_consts<V, CL>();
+  const LevelViewT<V, CL, CI> X = level_view_T(A);
+  const WaveLoop W = wave_loop(A.R.n());
+  for (uint32_t i = W.first; i < W.end; i += W.step) {
+    if (i < A.R.n_leaf) apply_T_brick<false>(X, L, A.R.leaf_lo + i, colour);
+    else apply_T_brick<true>(X, L, A.R.inner_lo + (i - A.R.n_leaf), colour);
+  }
 }
 
 // Coupling of level l to the coarser leaves, transposed: on the leaf bricks
@@ -846,18 +892,23 @@ __global__ void __launch_bounds__(kBlock) k_T_coarse(LevelArgsT<V, CL, CI> A) {
 template <class V, class CL, class CI>
 __global__ void __launch_bounds__(kBlock) k_T_fas(LevelArgsT<V, CL, CI> A) {
   if (A.done && *A.done) return;
-  uint32_t i = blockIdx.x * kWavesPerBlock + wave_id();
-  int m = threadIdx.x & (kWave - 1);
-  if (i >= A.R.n()) return;
-  uint32_t b = A.R.brick(i);
-  const BrickMeta M = A.T.meta[b];
-  V c = A.cf.get(b, 0, m), k0 = A.cf.get(b, 1, m), k1 = A.cf.get(b, 2, m),
-    k2 = A.cf.get(b, 3, m);
-  V t = level_AuT(A.cf, A.W, M, m, A.W[b * 64u + m], c, k0, k1, k2);
-  if (b < A.T.nlb)
-    A.RHO[b * 64u + m] += t;
-  else
-    A.SBAR[(b - A.T.nlb) * 64u + m] += t;
+  const LaneC<V, CL> L = lane_consts<V, CL>();
+  const LevelViewT<V, CL, CI> X = level_view_T(A);
+  const WaveLoop W = wave_loop(A.R.n());
+  for (uint32_t i = W.first; i < W.end; i += W.step) {
+    if (i < A.R.n_leaf) {
+      uint32_t b = A.R.leaf_lo + i;
+      const BrickMeta M = load_meta(X.c.meta, b);
+      V t = level_AuT<false>(X, L, b, M, bload<V>(X.w, L.m, b * 64u));
+      bstore<V>(X.rho, L.m, b * 64u, bload<V>(X.rho, L.m, b * 64u) + t);
+    } else {
+      uint32_t b = A.R.inner_lo + (i - A.R.n_leaf);
+      const BrickMeta M = load_meta(X.c.meta, b);
+      V t = level_AuT<true>(X, L, b, M, bload<V>(X.w, L.m, b * 64u));
+      uint32_t j = (b - X.c.nlb) * 64u;
+      bstore<V>(X.sbar, L.m, j, bload<V>(X.sbar, L.m, j) + t);
+    }
+  }
 }
 
 // On the bricks of level l: active cells RHO += SBAR_P / n_active(P),
@@ -886,36 +937,27 @@ __global__ void __launch_bounds__(kBlock) k_T_prolong(LevelArgsT<V, CL, CI> A) {
 }
 
 // Coarsest level, transposed: the half-sweeps of k_coarsest in reverse
-// order, each as w = RHO / c on the colour, Y += w, RHO -= A^T w.
+// order, each as w = RHO / c on the colour, then RHO -= A^T w, Y += w.
 template <class V, class CL, class CI>
 __global__ void __launch_bounds__(1024) k_T_coarsest(LevelArgsT<V, CL, CI> A, int nu) {
   if (A.done && *A.done) return;
+  const LaneC<V, CL> L = lane_consts<V, CL>();
+  const LevelViewT<V, CL, CI> X = level_view_T(A);
   uint32_t w = wave_id();
   uint32_t nw = blockDim.x / kWave;
-  int m = threadIdx.x & (kWave - 1);
   int half = nu / 2;
   for (int it = 0; it < nu; ++it) {
     for (int h2 = 0; h2 < 2; ++h2) {
       int colour = it < nu - half ? h2 : 1 - h2;
       for (uint32_t i = w; i < A.R.n(); i += nw) {
-        uint32_t b = A.R.brick(i);
-        const BrickMeta M = A.T.meta[b];
-        bool act = (act_mask(M) >> m) & 1ull;
-        int col = (dev_cx(m) + dev_cy(m) + dev_cz(m)) & 1;
-        V x = V(0);
-        if (act && col == colour) x = div_by(A.RHO[b * 64u + m], A.cf.get(b, 0, m));
-        A.W[b * 64u + m] = x;
-        A.Y[b * 64u + m] += x;
+        if (i < A.R.n_leaf) sweep_w_brick<false>(X, L, A.R.leaf_lo + i, colour);
+        else sweep_w_brick<true>(X, L, A.R.inner_lo + (i - A.R.n_leaf), colour);
       }
       __threadfence_block();
       __syncthreads();
       for (uint32_t i = w; i < A.R.n(); i += nw) {
-        uint32_t b = A.R.brick(i);
-        const BrickMeta M = A.T.meta[b];
-        V c = A.cf.get(b, 0, m), k0 = A.cf.get(b, 1, m), k1 = A.cf.get(b, 2, m),
-          k2 = A.cf.get(b, 3, m);
-        V t = level_AuT(A.cf, A.W, M, m, A.W[b * 64u + m], c, k0, k1, k2);
-        A.RHO[b * 64u + m] -= t;
+        if (i < A.R.n_leaf) apply_T_brick<false>(X, L, A.R.leaf_lo + i, colour);
+        else apply_T_brick<true>(X, L, A.R.inner_lo + (i - A.R.n_leaf), colour);
       }
       __threadfence_block();
       __syncthreads();
@@ -923,7 +965,6 @@ __global__ void __launch_bounds__(1024) k_T_coarsest(LevelArgsT<V, CL, CI> A, in
   }
 }
 
-// leaf part of the transposed cycle's residual from an FP64 leaf vector
 template <class V>
 __global__ void k_T_load(const double *src, V *dst, int64_t n) {
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;

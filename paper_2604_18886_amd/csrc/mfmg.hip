@@ -74,22 +74,36 @@ inline unsigned grid_for(int64_t bricks) {
   return unsigned(g > 0 ? g : 1);
 }
 // Grid of the level kernels (wave_loop): a multiple of 8 workgroups, at
-// most kMaxWavesPerXcd waves per XCD, each looping over its share of bricks.
-// The cap can be changed with the environment variable MFMG_WAVES_PER_XCD
-// (read once), for tuning.
-constexpr int64_t kMaxWavesPerXcd = 1024;
-inline int64_t waves_per_xcd() {
+// most waves_per_xcd waves per XCD, each looping over its share of bricks.
+// Measured on the finest level of the large workload: the FP32 stencils are
+// fastest with 2048 waves per XCD looping, the FP64 ones (more registers,
+// fewer waves resident) with one brick per wave.  Reductions over the
+// leaves keep the 2048 cap, so that one workgroup adds their partials.
+// MFMG_WAVES_PER_XCD (read once) overrides the cap, for tuning.
+constexpr int64_t kWavesPerXcd32 = 2048;
+constexpr int64_t kWavesPerXcd64 = int64_t(1) << 30;
+inline int64_t waves_override() {
   static const int64_t v = [] {
     const char *e = std::getenv("MFMG_WAVES_PER_XCD");
     long long x = e ? std::atoll(e) : 0;
-    return x > 0 ? int64_t(x) : kMaxWavesPerXcd;
+    return x > 0 ? int64_t(x) : int64_t(0);
   }();
   return v;
 }
-inline unsigned level_grid(int64_t bricks) {
+inline unsigned grid_waves(int64_t bricks, int64_t cap) {
   int64_t chunk = (bricks + 7) / 8;
-  int64_t waves = std::min<int64_t>(std::max<int64_t>(chunk, 1), waves_per_xcd());
+  int64_t waves = std::min<int64_t>(std::max<int64_t>(chunk, 1), cap);
   return unsigned(8 * ((waves + kWavesPerBlock - 1) / kWavesPerBlock));
+}
+// reductions and FP32 stencils
+inline unsigned level_grid(int64_t bricks) {
+  return grid_waves(bricks, waves_override() ? waves_override() : kWavesPerXcd32);
+}
+// stencils on values of type V
+template <class V>
+inline unsigned stencil_grid(int64_t bricks) {
+  if (waves_override()) return grid_waves(bricks, waves_override());
+  return grid_waves(bricks, sizeof(V) == 8 ? kWavesPerXcd64 : kWavesPerXcd32);
 }
 inline unsigned grid_elems(int64_t n, int t) { return unsigned(std::max<int64_t>(1, (n + t - 1) / t)); }
 
@@ -620,7 +634,8 @@ struct Cycle {
   }
 
   void half_sweep(const LevelArgs<V, CL, CI> &A, int colour) const {
-    hipLaunchKernelGGL((k_smooth<V, CL, CI>), dim3(level_grid(A.R.n())), dim3(kBlock), 0, s, A,
+    hipLaunchKernelGGL((k_smooth<V, CL, CI>), dim3(stencil_grid<V>(A.R.n())), dim3(kBlock), 0,
+                       s, A,
                        colour);
   }
   void smooth(int l, int first, int nu, bool zero_start = false) const {
@@ -630,7 +645,7 @@ struct Cycle {
       for (int c = 0; c < 2; ++c) {
         int colour = c == 0 ? first : 1 - first;
         if (zero_start && it == 0 && c == 0)
-          hipLaunchKernelGGL((k_smooth_zero<V, CL, CI>), dim3(level_grid(A.R.n())),
+          hipLaunchKernelGGL((k_smooth_zero<V, CL, CI>), dim3(stencil_grid<V>(A.R.n())),
                              dim3(kBlock), 0, s, A, colour);
         else
           half_sweep(A, colour);
@@ -652,14 +667,17 @@ struct Cycle {
     smooth(l, 0, p.nu_pre, zero_start);
     auto A = args(l, false);
     V scale = V(p.beta_mg / p.alpha);
-    hipLaunchKernelGGL((k_restrict<V, CL, CI>), dim3(level_grid(A.R.n())), dim3(kBlock), 0, s,
+    hipLaunchKernelGGL((k_restrict<V, CL, CI>), dim3(stencil_grid<V>(A.R.n())), dim3(kBlock),
+                       0, s,
                        A, scale);
     auto C = args(l - 1, true);
     if (C.R.n())
-      hipLaunchKernelGGL((k_fas_rhs<V, CL, CI>), dim3(level_grid(C.R.n_inner)), dim3(kBlock), 0,
+      hipLaunchKernelGGL((k_fas_rhs<V, CL, CI>), dim3(stencil_grid<V>(C.R.n_inner)),
+                         dim3(kBlock), 0,
                          s, C);
     for (int k = 0; k < p.mu; ++k) fas(l - 1);
-    hipLaunchKernelGGL((k_prolong<V, CL, CI>), dim3(level_grid(A.R.n())), dim3(kBlock), 0, s,
+    hipLaunchKernelGGL((k_prolong<V, CL, CI>), dim3(stencil_grid<V>(A.R.n())), dim3(kBlock),
+                       0, s,
                        A);
     smooth(l, 1, p.nu_post);
   }
@@ -697,6 +715,7 @@ struct CycleT {
   const CL *leafc;
   const CI *innerc;
   const CL *tc;
+  const CL *pf;
   V *RHO, *Y, *W, *SBAR, *YS;
   hipStream_t s;
   const int *done;
@@ -725,11 +744,15 @@ struct CycleT {
     }
     A.bscale = V(h->prm.beta_mg / h->prm.alpha);
     A.done = done;
+    A.pf = pf;
     return A;
   }
-  void launch_apply(int l) const {
+  // colour >= 0: the apply step of a transposed half-sweep of that colour
+  void launch_apply(int l, int colour) const {
     auto A = args(l, 0);
-    hipLaunchKernelGGL((k_T_apply<V, CL, CI>), dim3(grid_for(A.R.n())), dim3(kBlock), 0, s, A);
+    hipLaunchKernelGGL((k_T_apply<V, CL, CI>), dim3(stencil_grid<V>(A.R.n())), dim3(kBlock),
+                       0, s,
+                       A, colour);
     if (l > h->lc) {
       auto C = args(l - 1, 1);
       if (C.R.n())
@@ -743,9 +766,11 @@ struct CycleT {
     if (A.R.n() == 0) return;
     for (int it = 0; it < nu; ++it)
       for (int c = 0; c < 2; ++c) {
-        hipLaunchKernelGGL((k_T_sweep_w<V, CL, CI>), dim3(grid_for(A.R.n())), dim3(kBlock), 0,
-                           s, A, c == 0 ? first : 1 - first);
-        launch_apply(l);
+        int colour = c == 0 ? first : 1 - first;
+        hipLaunchKernelGGL((k_T_sweep_w<V, CL, CI>), dim3(stencil_grid<V>(A.R.n())),
+                           dim3(kBlock), 0,
+                           s, A, colour);
+        launch_apply(l, colour);
       }
   }
   void fas_T(int l) const {
@@ -764,10 +789,11 @@ struct CycleT {
     for (int k = 0; k < p.mu; ++k) fas_T(l - 1);
     auto C = args(l - 1, 0);
     hipLaunchKernelGGL((k_T_coarse<V, CL, CI>), dim3(grid_for(C.R.n())), dim3(kBlock), 0, s, C);
-    hipLaunchKernelGGL((k_T_fas<V, CL, CI>), dim3(grid_for(C.R.n())), dim3(kBlock), 0, s, C);
+    hipLaunchKernelGGL((k_T_fas<V, CL, CI>), dim3(stencil_grid<V>(C.R.n())), dim3(kBlock), 0,
+                       s, C);
     hipLaunchKernelGGL((k_T_prolong<V, CL, CI>), dim3(grid_for(A.R.n())), dim3(kBlock), 0, s,
                        A);
-    launch_apply(l);
+    launch_apply(l, -1);
     smooth_T(l, 1, p.nu_pre);  // forward pre-smoothing is (R,B)^nu
   }
   // input: an FP64 leaf vector in device order
@@ -796,16 +822,16 @@ void run_cycle_T(mfmg_hierarchy *h, const double *r, hipStream_t s,
                  const int *done = nullptr) {
   if (h->prm.precision == MFMG_MIXED) {
     alloc_transpose(h, h->T32);
-    CycleT<float, float, __half> c{h, h->coef32.p, h->coef16.p, h->tc32.p, h->T32[0].p,
-                                   h->T32[1].p, h->T32[2].p, h->T32[3].p, h->T32[4].p, s,
-                                   done};
+    CycleT<float, float, __half> c{h, h->coef32.p, h->coef16.p, h->tc32.p, h->pf32.p,
+                                   h->T32[0].p, h->T32[1].p, h->T32[2].p, h->T32[3].p,
+                                   h->T32[4].p, s, done};
     c.run(r);
   } else {
     alloc_transpose(h, h->T64);
     CycleT<double, double, double> c{h, h->coef64.p,
                                      h->coef64.p + int64_t(h->co->dt->nlb) * 256,
-                                     h->co->tc.p, h->T64[0].p, h->T64[1].p, h->T64[2].p,
-                                     h->T64[3].p, h->T64[4].p, s, done};
+                                     h->co->tc.p, h->pf64.p, h->T64[0].p, h->T64[1].p,
+                                     h->T64[2].p, h->T64[3].p, h->T64[4].p, s, done};
     c.run(r);
   }
 }
