@@ -686,6 +686,7 @@ struct LevelArgsT {
   V *RHO;    // nb * 64
   V *Y;      // nb * 64
   V *W;      // nb * 64
+  V *W2;     // nb * 64: the next transposed half-sweep's W (written by k_T_apply)
   V *SBAR;   // (nb - nlb) * 64
   V *YS;     // (nb - nlb) * 64
   Range R;
@@ -698,7 +699,7 @@ struct LevelArgsT {
 template <class V, class CL, class CI>
 struct LevelViewT {
   LevelView<V, CL, CI> c;  // coefficients and plus faces (u = W)
-  __amdgpu_buffer_rsrc_t rho, y, w, sbar, ys;
+  __amdgpu_buffer_rsrc_t rho, y, w, w2, sbar, ys;
 };
 
 template <class V, class CL, class CI>
@@ -708,6 +709,7 @@ __device__ __forceinline__ LevelViewT<V, CL, CI> level_view_T(const LevelArgsT<V
   X.rho = make_rsrc(A.RHO, nb * 64 * sizeof(V));
   X.y = make_rsrc(A.Y, nb * 64 * sizeof(V));
   X.w = make_rsrc(A.W, nb * 64 * sizeof(V));
+  X.w2 = make_rsrc(A.W2, nb * 64 * sizeof(V));
   X.sbar = make_rsrc(A.SBAR, (nb - nlb) * 64 * sizeof(V));
   X.ys = make_rsrc(A.YS, (nb - nlb) * 64 * sizeof(V));
   X.c.u = X.w;
@@ -731,13 +733,14 @@ __device__ __forceinline__ LevelViewT<V, CL, CI> level_view_T(const LevelArgsT<V
 // neighbour sum by themselves.
 template <bool INNER, class V, class CL, class CI>
 __device__ __forceinline__ V level_AuT(const LevelViewT<V, CL, CI> &X, const LaneC<V, CL> &L,
-                                       uint32_t b, const BrickMeta &M, V w) {
+                                       uint32_t b, const BrickMeta &M, V w, V &diag) {
   V k0 = own_coef<INNER>(X.c, b, 1, L.m);
   V k1 = own_coef<INNER>(X.c, b, 2, L.m);
   V k2 = own_coef<INNER>(X.c, b, 3, L.m);
   V v[6], k[6];
   face_values(X.w, X.c.pf, L, b, M, w, k0, k1, k2, v, k);
   V c = ((k[0] + k[1]) + (k[2] + k[3])) + (k[4] + k[5]);
+  diag = c;
   uint64_t amask = act_mask(M);
   bool act = (amask >> L.m) & 1ull;
   V acc = c * w;
@@ -787,26 +790,36 @@ __global__ void __launch_bounds__(kBlock) k_T_sweep_w(LevelArgsT<V, CL, CI> A, i
 
 // RHO -= A^T W on the bricks of the range; with colour >= 0 (a transposed
 // half-sweep) also Y += W on that colour's cells (W is zero elsewhere).
+// With next >= 0 the first step of the following half-sweep is taken too:
+// W2 = RHO / c on the active cells of colour next (own cells only, so no
+// other wave needs them during this launch), 0 elsewhere.
 template <bool INNER, class V, class CL, class CI>
 __device__ __forceinline__ void apply_T_brick(const LevelViewT<V, CL, CI> &X,
-                                              const LaneC<V, CL> &L, uint32_t b, int colour) {
+                                              const LaneC<V, CL> &L, uint32_t b, int colour,
+                                              int next) {
   const BrickMeta M = load_meta(X.c.meta, b);
   V w = bload<V>(X.w, L.m, b * 64u);
-  V t = level_AuT<INNER>(X, L, b, M, w);
-  V rho = bload<V>(X.rho, L.m, b * 64u);
-  bstore<V>(X.rho, L.m, b * 64u, rho - t);
+  V c;
+  V t = level_AuT<INNER>(X, L, b, M, w, c);
+  V rho = bload<V>(X.rho, L.m, b * 64u) - t;
+  bstore<V>(X.rho, L.m, b * 64u, rho);
   if (L.colour == colour) bstore<V>(X.y, L.m, b * 64u, bload<V>(X.y, L.m, b * 64u) + w);
+  if (next >= 0) {
+    bool act = (act_mask(M) >> L.m) & 1ull;
+    bstore<V>(X.w2, L.m, b * 64u, act && L.colour == next ? div_by(rho, c) : V(0));
+  }
 }
 
 template <class V, class CL, class CI>
-__global__ void __launch_bounds__(kBlock) k_T_apply(LevelArgsT<V, CL, CI> A, int colour) {
+__global__ void __launch_bounds__(kBlock) k_T_apply(LevelArgsT<V, CL, CI> A, int colour,
+                                                    int next) {
   if (A.done && *A.done) return;
   const LaneC<V, CL> L = lane_consts<V, CL>();
   const LevelViewT<V, CL, CI> X = level_view_T(A);
   const WaveLoop W = wave_loop(A.R.n());
   for (uint32_t i = W.first; i < W.end; i += W.step) {
-    if (i < A.R.n_leaf) apply_T_brick<false>(X, L, A.R.leaf_lo + i, colour);
-    else apply_T_brick<true>(X, L, A.R.inner_lo + (i - A.R.n_leaf), colour);
+    if (i < A.R.n_leaf) apply_T_brick<false>(X, L, A.R.leaf_lo + i, colour, next);
+    else apply_T_brick<true>(X, L, A.R.inner_lo + (i - A.R.n_leaf), colour, next);
   }
 }
 
@@ -899,12 +912,14 @@ __global__ void __launch_bounds__(kBlock) k_T_fas(LevelArgsT<V, CL, CI> A) {
     if (i < A.R.n_leaf) {
       uint32_t b = A.R.leaf_lo + i;
       const BrickMeta M = load_meta(X.c.meta, b);
-      V t = level_AuT<false>(X, L, b, M, bload<V>(X.w, L.m, b * 64u));
+      V c;
+      V t = level_AuT<false>(X, L, b, M, bload<V>(X.w, L.m, b * 64u), c);
       bstore<V>(X.rho, L.m, b * 64u, bload<V>(X.rho, L.m, b * 64u) + t);
     } else {
       uint32_t b = A.R.inner_lo + (i - A.R.n_leaf);
       const BrickMeta M = load_meta(X.c.meta, b);
-      V t = level_AuT<true>(X, L, b, M, bload<V>(X.w, L.m, b * 64u));
+      V c;
+      V t = level_AuT<true>(X, L, b, M, bload<V>(X.w, L.m, b * 64u), c);
       uint32_t j = (b - X.c.nlb) * 64u;
       bstore<V>(X.sbar, L.m, j, bload<V>(X.sbar, L.m, j) + t);
     }
@@ -956,8 +971,8 @@ __global__ void __launch_bounds__(1024) k_T_coarsest(LevelArgsT<V, CL, CI> A, in
       __threadfence_block();
       __syncthreads();
       for (uint32_t i = w; i < A.R.n(); i += nw) {
-        if (i < A.R.n_leaf) apply_T_brick<false>(X, L, A.R.leaf_lo + i, colour);
-        else apply_T_brick<true>(X, L, A.R.inner_lo + (i - A.R.n_leaf), colour);
+        if (i < A.R.n_leaf) apply_T_brick<false>(X, L, A.R.leaf_lo + i, colour, -1);
+        else apply_T_brick<true>(X, L, A.R.inner_lo + (i - A.R.n_leaf), colour, -1);
       }
       __threadfence_block();
       __syncthreads();

@@ -171,8 +171,8 @@ struct mfmg_hierarchy {
   DevBuf<Scalars> S;
   DevBuf<double> hist;
   // transposed cycle (allocated on first use): residual, solution, scratch
-  DevBuf<double> T64[5];          // RHO, Y, W (nb*64), SBAR, YS ((nb-nlb)*64)
-  DevBuf<float> T32[5];
+  DevBuf<double> T64[6];  // RHO, Y, W (nb*64), SBAR, YS ((nb-nlb)*64), W2 (nb*64)
+  DevBuf<float> T32[6];
   DevBuf<double> rA;              // adjoint PCG residual
   // face arrays for the per-face gradient (allocated on first use)
   DevBuf<int64_t> f_owner, f_other;
@@ -716,7 +716,7 @@ struct CycleT {
   const CI *innerc;
   const CL *tc;
   const CL *pf;
-  V *RHO, *Y, *W, *SBAR, *YS;
+  V *RHO, *Y, *W, *SBAR, *YS, *W2;
   hipStream_t s;
   const int *done;
 
@@ -735,6 +735,7 @@ struct CycleT {
     A.RHO = RHO;
     A.Y = Y;
     A.W = W;
+    A.W2 = W2;
     A.SBAR = SBAR;
     A.YS = YS;
     A.R = D.range[l];
@@ -747,31 +748,42 @@ struct CycleT {
     A.pf = pf;
     return A;
   }
-  // colour >= 0: the apply step of a transposed half-sweep of that colour
-  void launch_apply(int l, int colour) const {
+  // RHO -= A^T w, w in buffer win, and the coupling of w to the coarser
+  // level's leaves; colour >= 0: the apply step of a transposed half-sweep
+  // of that colour; next >= 0: also the next half-sweep's w, into wout
+  void launch_apply(int l, int colour, V *win, int next = -1, V *wout = nullptr) const {
     auto A = args(l, 0);
+    A.W = win;
+    A.W2 = wout ? wout : win;
     hipLaunchKernelGGL((k_T_apply<V, CL, CI>), dim3(stencil_grid<V>(A.R.n())), dim3(kBlock),
-                       0, s,
-                       A, colour);
+                       0, s, A, colour, next);
     if (l > h->lc) {
       auto C = args(l - 1, 1);
+      C.W = win;
       if (C.R.n())
         hipLaunchKernelGGL((k_T_coupling<V, CL, CI>), dim3(grid_for(C.R.n())), dim3(kBlock), 0,
                            s, C);
     }
   }
-  // transpose of smooth(l, (c0, 1 - c0), nu): colours in reversed order
-  void smooth_T(int l, int first, int nu) const {
+  // Transpose of smooth(l, (c0, 1 - c0), nu): 2 nu half-sweeps with the
+  // colours in reversed order.  Each apply step also forms the w of the
+  // half-sweep after it, alternating between W2 and W: the first w is in
+  // W2 and the last in W (2 nu - 1 is odd).  w_ready: the caller's last
+  // apply already put the first w in W2.
+  void smooth_T(int l, int first, int nu, bool w_ready = false) const {
     auto A = args(l, 0);
-    if (A.R.n() == 0) return;
-    for (int it = 0; it < nu; ++it)
-      for (int c = 0; c < 2; ++c) {
-        int colour = c == 0 ? first : 1 - first;
-        hipLaunchKernelGGL((k_T_sweep_w<V, CL, CI>), dim3(stencil_grid<V>(A.R.n())),
-                           dim3(kBlock), 0,
-                           s, A, colour);
-        launch_apply(l, colour);
-      }
+    if (A.R.n() == 0 || nu == 0) return;
+    if (!w_ready) {
+      A.W = W2;
+      hipLaunchKernelGGL((k_T_sweep_w<V, CL, CI>), dim3(stencil_grid<V>(A.R.n())),
+                         dim3(kBlock), 0, s, A, first);
+    }
+    V *buf[2] = {W2, W};
+    for (int k = 0; k < 2 * nu; ++k) {
+      int colour = (k & 1) ? 1 - first : first;
+      int next = k + 1 < 2 * nu ? 1 - colour : -1;
+      launch_apply(l, colour, buf[k & 1], next, buf[(k & 1) ^ 1]);
+    }
   }
   void fas_T(int l) const {
     const mfmg_mg_params &p = h->prm;
@@ -793,8 +805,13 @@ struct CycleT {
                        s, C);
     hipLaunchKernelGGL((k_T_prolong<V, CL, CI>), dim3(grid_for(A.R.n())), dim3(kBlock), 0, s,
                        A);
-    launch_apply(l, -1);
-    smooth_T(l, 1, p.nu_pre);  // forward pre-smoothing is (R,B)^nu
+    // forward pre-smoothing is (R,B)^nu; its transpose starts with colour 1
+    if (p.nu_pre > 0) {
+      launch_apply(l, -1, W, 1, W2);
+      smooth_T(l, 1, p.nu_pre, true);
+    } else {
+      launch_apply(l, -1, W);
+    }
   }
   // input: an FP64 leaf vector in device order
   void run(const double *in) const {
@@ -809,11 +826,12 @@ struct CycleT {
 };
 
 template <class V>
-void alloc_transpose(const mfmg_hierarchy *hc, DevBuf<V> (&T)[5]) {
+void alloc_transpose(const mfmg_hierarchy *hc, DevBuf<V> (&T)[6]) {
   if (T[0].p) return;
   int64_t nb = hc->co->dt->nb, nlb = hc->co->dt->nlb;
   for (int i = 0; i < 3; ++i) T[i].alloc(size_t(nb) * 64);
   for (int i = 3; i < 5; ++i) T[i].alloc(size_t(nb - nlb) * 64 + 1);
+  T[5].alloc(size_t(nb) * 64);
 }
 
 // z = M^T r: r, z FP64 leaf vectors in device order; returns the z buffer
@@ -824,14 +842,15 @@ void run_cycle_T(mfmg_hierarchy *h, const double *r, hipStream_t s,
     alloc_transpose(h, h->T32);
     CycleT<float, float, __half> c{h, h->coef32.p, h->coef16.p, h->tc32.p, h->pf32.p,
                                    h->T32[0].p, h->T32[1].p, h->T32[2].p, h->T32[3].p,
-                                   h->T32[4].p, s, done};
+                                   h->T32[4].p, h->T32[5].p, s, done};
     c.run(r);
   } else {
     alloc_transpose(h, h->T64);
     CycleT<double, double, double> c{h, h->coef64.p,
                                      h->coef64.p + int64_t(h->co->dt->nlb) * 256,
                                      h->co->tc.p, h->pf64.p, h->T64[0].p, h->T64[1].p,
-                                     h->T64[2].p, h->T64[3].p, h->T64[4].p, s, done};
+                                     h->T64[2].p, h->T64[3].p, h->T64[4].p, h->T64[5].p, s,
+                                     done};
     c.run(r);
   }
 }
