@@ -90,25 +90,25 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint6
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, int(n), kRsrcWord3);
 }
 
-template <class T>
-__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, uint32_t lane, uint32_t base);
-template <>
-__device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, uint32_t lane,
-                                              uint32_t base) {
-  return __builtin_bit_cast(
-      float, __builtin_amdgcn_raw_buffer_load_b32(r, int(lane * 4u), int(base * 4u), 0));
-}
-template <>
-__device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, uint32_t lane,
-                                                uint32_t base) {
-  return __builtin_bit_cast(
-      double, __builtin_amdgcn_raw_buffer_load_b64(r, int(lane * 8u), int(base * 8u), 0));
-}
-template <>
-__device__ __forceinline__ __half bload<__half>(__amdgpu_buffer_rsrc_t r, uint32_t lane,
-                                                uint32_t base) {
-  return __builtin_bit_cast(
-      __half, __builtin_amdgcn_raw_buffer_load_b16(r, int(lane * 2u), int(base * 2u), 0));
+// Cache-policy operand of a buffer load (gfx950): 0 = default, 2 = nt
+// (non-temporal: the line is a first candidate for eviction from L2).
+constexpr int kCpolDefault = 0;
+constexpr int kCpolStream = 2;
+
+// Load of element `lane` of the array at element offset `base` (the lane
+// offset goes to voffset, the uniform base to soffset).
+template <class T, int CPOL = kCpolDefault>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, uint32_t lane, uint32_t base) {
+  constexpr uint32_t n = sizeof(T);
+  if constexpr (n == 8)
+    return __builtin_bit_cast(
+        T, __builtin_amdgcn_raw_buffer_load_b64(r, int(lane * n), int(base * n), CPOL));
+  else if constexpr (n == 4)
+    return __builtin_bit_cast(
+        T, __builtin_amdgcn_raw_buffer_load_b32(r, int(lane * n), int(base * n), CPOL));
+  else
+    return __builtin_bit_cast(
+        T, __builtin_amdgcn_raw_buffer_load_b16(r, int(lane * n), int(base * n), CPOL));
 }
 
 template <class T>

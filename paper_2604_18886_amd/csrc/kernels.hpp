@@ -397,7 +397,12 @@ __device__ __forceinline__ WaveLoop wave_loop(uint32_t n) {
   return {lo + j, hi, (gridDim.x >> 3) * kWavesPerBlock};
 }
 
-template <class V, class CL, class CI>
+// CP: cache policy of the loads whose data a launch uses once (coefficient
+// arrays, plus-face table, right-hand side).  On a level larger than the
+// Infinity Cache these are loaded non-temporal, so that the iterate -- the
+// only array read again for neighbouring bricks -- keeps the L2; on smaller
+// levels everything stays cached for the next half-sweep.
+template <class V, class CL, class CI, int CP = kCpolDefault>
 struct LevelView {
   __amdgpu_buffer_rsrc_t u, b, us, cl, ci, pf;
   const BrickMeta *meta;
@@ -405,9 +410,9 @@ struct LevelView {
   V iscale;
 };
 
-template <class V, class CL, class CI>
-__device__ __forceinline__ LevelView<V, CL, CI> level_view(const LevelArgs<V, CL, CI> &A) {
-  LevelView<V, CL, CI> X;
+template <int CP = kCpolDefault, class V, class CL, class CI>
+__device__ __forceinline__ LevelView<V, CL, CI, CP> level_view(const LevelArgs<V, CL, CI> &A) {
+  LevelView<V, CL, CI, CP> X;
   uint64_t nb = A.T.nb, nlb = A.T.nlb;
   X.u = make_rsrc(A.U, nb * 64 * sizeof(V));
   X.b = make_rsrc(A.B, nb * 64 * sizeof(V));
@@ -424,26 +429,29 @@ __device__ __forceinline__ LevelView<V, CL, CI> level_view(const LevelArgs<V, CL
 // Coefficient comp (0 = c, 1 + a = k_a) of the lane's cell of brick b;
 // INNER selects the inner-brick array (FP16 in mixed precision, stored
 // divided by the cell size).
-template <bool INNER, class V, class CL, class CI>
-__device__ __forceinline__ V own_coef(const LevelView<V, CL, CI> &X, uint32_t b, int comp,
+template <bool INNER, class V, class CL, class CI, int CP>
+__device__ __forceinline__ V own_coef(const LevelView<V, CL, CI, CP> &X, uint32_t b, int comp,
                                       uint32_t m) {
   if constexpr (INNER) {
-    V v = V(bload<CI>(X.ci, m, (b - X.nlb) * 256u + uint32_t(comp) * 64u));
+    V v = V(bload<CI, CP>(X.ci, m, (b - X.nlb) * 256u + uint32_t(comp) * 64u));
     if constexpr (std::is_same<CL, CI>::value) return v;
     else return v * X.iscale;
   } else {
-    return V(bload<CL>(X.cl, m, b * 256u + uint32_t(comp) * 64u));
+    return V(bload<CL, CP>(X.cl, m, b * 256u + uint32_t(comp) * 64u));
   }
 }
 
-template <class T>
+template <class T, int CPOL = kCpolDefault>
 __device__ __forceinline__ T bload_bytes(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
   if constexpr (sizeof(T) == 8)
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, int(voff), int(soff), 0));
+    return __builtin_bit_cast(
+        T, __builtin_amdgcn_raw_buffer_load_b64(r, int(voff), int(soff), CPOL));
   else if constexpr (sizeof(T) == 4)
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, int(voff), int(soff), 0));
+    return __builtin_bit_cast(
+        T, __builtin_amdgcn_raw_buffer_load_b32(r, int(voff), int(soff), CPOL));
   else
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, int(voff), int(soff), 0));
+    return __builtin_bit_cast(
+        T, __builtin_amdgcn_raw_buffer_load_b16(r, int(voff), int(soff), CPOL));
 }
 
 // Neighbour sum of the level operator at the lane's cell of brick b:
@@ -463,7 +471,7 @@ __device__ __forceinline__ T bload_bytes(__amdgpu_buffer_rsrc_t r, uint32_t voff
 // v[d] the same-level neighbour's entry of the vector in buffer x (0 at a
 // wall or T-face, where the load is out of range), k[d] the face
 // coefficient (own k_a on the minus side, the neighbour's on the plus side).
-template <class V, class CL>
+template <int CP, class V, class CL>
 __device__ __forceinline__ void face_values(__amdgpu_buffer_rsrc_t x, __amdgpu_buffer_rsrc_t pf,
                                             const LaneC<V, CL> &L, uint32_t b,
                                             const BrickMeta &M, V u, V k0, V k1, V k2, V (&v)[6],
@@ -478,7 +486,7 @@ __device__ __forceinline__ void face_values(__amdgpu_buffer_rsrc_t x, __amdgpu_b
     V vs = shfl(u, L.p[d]);
     v[d] = L.out[d] ? vl : vs;
     if (d & 1) {
-      V kl = V(bload_bytes<CL>(pf, L.foff[a], b * uint32_t(48 * sizeof(CL))));
+      V kl = V(bload_bytes<CL, CP>(pf, L.foff[a], b * uint32_t(48 * sizeof(CL))));
       V ks = shfl(kown, L.p[d]);
       k[d] = L.out[d] ? kl : ks;
     } else {
@@ -487,12 +495,12 @@ __device__ __forceinline__ void face_values(__amdgpu_buffer_rsrc_t x, __amdgpu_b
   }
 }
 
-template <class V, class CL, class CI>
-__device__ __forceinline__ V stencil_sum(const LevelView<V, CL, CI> &X, const LaneC<V, CL> &L,
+template <class V, class CL, class CI, int CP>
+__device__ __forceinline__ V stencil_sum(const LevelView<V, CL, CI, CP> &X, const LaneC<V, CL> &L,
                                          uint32_t b, const BrickMeta &M, V u, V k0, V k1,
                                          V k2, V &diag) {
   V v[6], k[6];
-  face_values(X.u, X.pf, L, b, M, u, k0, k1, k2, v, k);
+  face_values<CP>(X.u, X.pf, L, b, M, u, k0, k1, k2, v, k);
   if (M.flags & kFlagT) {
     uint64_t amask = act_mask(M);
     bool act = (amask >> L.m) & 1ull;
@@ -520,26 +528,26 @@ __device__ __forceinline__ V stencil_sum(const LevelView<V, CL, CI> &X, const La
 // One brick of a colour half-sweep of red-black Gauss-Seidel: on the cells
 // of the colour u_m = (b_m + S_m) / c_m, every read taken before the write
 // (the neighbours of a cell all have the other colour).
-template <bool INNER, class V, class CL, class CI>
-__device__ __forceinline__ void smooth_brick(const LevelView<V, CL, CI> &X, const LaneC<V, CL> &L,
+template <bool INNER, class V, class CL, class CI, int CP>
+__device__ __forceinline__ void smooth_brick(const LevelView<V, CL, CI, CP> &X, const LaneC<V, CL> &L,
                                              uint32_t b, int colour) {
   const BrickMeta M = load_meta(X.meta, b);
   V k0 = own_coef<INNER>(X, b, 1, L.m);
   V k1 = own_coef<INNER>(X, b, 2, L.m);
   V k2 = own_coef<INNER>(X, b, 3, L.m);
   V u = bload<V>(X.u, L.m, b * 64u);
-  V rhs = bload<V>(X.b, L.m, b * 64u);
+  V rhs = bload<V, CP>(X.b, L.m, b * 64u);
   V c;
   V S = stencil_sum(X, L, b, M, u, k0, k1, k2, c);
   bool act = (act_mask(M) >> L.m) & 1ull;
   if (act && L.colour == colour) bstore<V>(X.u, L.m, b * 64u, div_by(rhs + S, c));
 }
 
-template <class V, class CL, class CI>
+template <class V, class CL, class CI, int CP = kCpolDefault>
 __global__ void __launch_bounds__(kBlock) k_smooth(LevelArgs<V, CL, CI> A, int colour) {
   if (A.done && *A.done) return;
   const LaneC<V, CL> L = lane_consts<V, CL>();
-  const LevelView<V, CL, CI> X = level_view(A);
+  const LevelView<V, CL, CI, CP> X = level_view<CP>(A);
   const WaveLoop W = wave_loop(A.R.n());
   for (uint32_t i = W.first; i < W.end; i += W.step) {
     if (i < A.R.n_leaf) smooth_brick<false>(X, L, A.R.leaf_lo + i, colour);
@@ -551,18 +559,18 @@ __global__ void __launch_bounds__(kBlock) k_smooth(LevelArgs<V, CL, CI> A, int c
 // iterate: every neighbour, ghost and wall value is 0, so the sweep sets
 // u = b / c on the cells of the colour and 0 on all others (which also
 // clears the iterate).
-template <class V, class CL, class CI>
+template <class V, class CL, class CI, int CP = kCpolDefault>
 __global__ void __launch_bounds__(kBlock) k_smooth_zero(LevelArgs<V, CL, CI> A, int colour) {
   if (A.done && *A.done) return;
   const LaneC<V, CL> L = lane_consts<V, CL>();
-  const LevelView<V, CL, CI> X = level_view(A);
+  const LevelView<V, CL, CI, CP> X = level_view<CP>(A);
   const WaveLoop W = wave_loop(A.R.n_leaf);
   for (uint32_t i = W.first; i < W.end; i += W.step) {
     uint32_t b = A.R.leaf_lo + i;
     const BrickMeta M = load_meta(X.meta, b);
     bool act = (act_mask(M) >> L.m) & 1ull;
     V c = own_coef<false>(X, b, 0, L.m);
-    V rhs = bload<V>(X.b, L.m, b * 64u);
+    V rhs = bload<V, CP>(X.b, L.m, b * 64u);
     bstore<V>(X.u, L.m, b * 64u, act && L.colour == colour ? div_by(rhs, c) : V(0));
   }
 }
@@ -571,15 +579,16 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zero(LevelArgs<V, CL, CI> A, 
 // its parent cells:  b_P = beta_mg (1/alpha) sum_children r,
 // u_P = u*_P = mean of the active children (k_fas_rhs then adds
 // A^{l-1} u* on inner cells).
-template <bool INNER, class V, class CL, class CI>
-__device__ __forceinline__ void restrict_brick(const LevelView<V, CL, CI> &X, const LaneC<V, CL> &L,
+template <bool INNER, class V, class CL, class CI, int CP>
+__device__ __forceinline__ void restrict_brick(const LevelView<V, CL, CI, CP> &X,
+                                               const LaneC<V, CL> &L,
                                                uint32_t b, V scale) {
   const BrickMeta M = load_meta(X.meta, b);
   V k0 = own_coef<INNER>(X, b, 1, L.m);
   V k1 = own_coef<INNER>(X, b, 2, L.m);
   V k2 = own_coef<INNER>(X, b, 3, L.m);
   V u = bload<V>(X.u, L.m, b * 64u);
-  V rhs = bload<V>(X.b, L.m, b * 64u);
+  V rhs = bload<V, CP>(X.b, L.m, b * 64u);
   V c;
   V S = stencil_sum(X, L, b, M, u, k0, k1, k2, c);
   uint64_t amask = act_mask(M);
@@ -598,11 +607,11 @@ __device__ __forceinline__ void restrict_brick(const LevelView<V, CL, CI> &X, co
   }
 }
 
-template <class V, class CL, class CI>
+template <class V, class CL, class CI, int CP = kCpolDefault>
 __global__ void __launch_bounds__(kBlock) k_restrict(LevelArgs<V, CL, CI> A, V scale) {
   if (A.done && *A.done) return;
   const LaneC<V, CL> L = lane_consts<V, CL>();
-  const LevelView<V, CL, CI> X = level_view(A);
+  const LevelView<V, CL, CI, CP> X = level_view<CP>(A);
   const WaveLoop W = wave_loop(A.R.n());
   for (uint32_t i = W.first; i < W.end; i += W.step) {
     if (i < A.R.n_leaf) restrict_brick<false>(X, L, A.R.leaf_lo + i, scale);
@@ -696,15 +705,15 @@ struct LevelArgsT {
 };
 
 // Buffer view of the transposed cycle's arrays on one level.
-template <class V, class CL, class CI>
+template <class V, class CL, class CI, int CP = kCpolDefault>
 struct LevelViewT {
-  LevelView<V, CL, CI> c;  // coefficients and plus faces (u = W)
+  LevelView<V, CL, CI, CP> c;  // coefficients and plus faces (u = W)
   __amdgpu_buffer_rsrc_t rho, y, w, w2, sbar, ys;
 };
 
-template <class V, class CL, class CI>
-__device__ __forceinline__ LevelViewT<V, CL, CI> level_view_T(const LevelArgsT<V, CL, CI> &A) {
-  LevelViewT<V, CL, CI> X;
+template <int CP = kCpolDefault, class V, class CL, class CI>
+__device__ __forceinline__ LevelViewT<V, CL, CI, CP> level_view_T(const LevelArgsT<V, CL, CI> &A) {
+  LevelViewT<V, CL, CI, CP> X;
   uint64_t nb = A.T.nb, nlb = A.T.nlb;
   X.rho = make_rsrc(A.RHO, nb * 64 * sizeof(V));
   X.y = make_rsrc(A.Y, nb * 64 * sizeof(V));
@@ -731,14 +740,14 @@ __device__ __forceinline__ LevelViewT<V, CL, CI> level_view_T(const LevelArgsT<V
 // (the coupling to the coarser level, B^T, is applied by k_T_coupling).  The
 // loads across T-faces are out of range, so those faces drop out of the
 // neighbour sum by themselves.
-template <bool INNER, class V, class CL, class CI>
-__device__ __forceinline__ V level_AuT(const LevelViewT<V, CL, CI> &X, const LaneC<V, CL> &L,
+template <bool INNER, class V, class CL, class CI, int CP>
+__device__ __forceinline__ V level_AuT(const LevelViewT<V, CL, CI, CP> &X, const LaneC<V, CL> &L,
                                        uint32_t b, const BrickMeta &M, V w, V &diag) {
   V k0 = own_coef<INNER>(X.c, b, 1, L.m);
   V k1 = own_coef<INNER>(X.c, b, 2, L.m);
   V k2 = own_coef<INNER>(X.c, b, 3, L.m);
   V v[6], k[6];
-  face_values(X.w, X.c.pf, L, b, M, w, k0, k1, k2, v, k);
+  face_values<CP>(X.w, X.c.pf, L, b, M, w, k0, k1, k2, v, k);
   V c = ((k[0] + k[1]) + (k[2] + k[3])) + (k[4] + k[5]);
   diag = c;
   uint64_t amask = act_mask(M);
@@ -765,8 +774,8 @@ __device__ __forceinline__ V level_AuT(const LevelViewT<V, CL, CI> &X, const Lan
 
 // First half of a transposed half-sweep: W = RHO / c on the active cells of
 // the colour, 0 elsewhere.
-template <bool INNER, class V, class CL, class CI>
-__device__ __forceinline__ void sweep_w_brick(const LevelViewT<V, CL, CI> &X,
+template <bool INNER, class V, class CL, class CI, int CP>
+__device__ __forceinline__ void sweep_w_brick(const LevelViewT<V, CL, CI, CP> &X,
                                               const LaneC<V, CL> &L, uint32_t b, int colour) {
   const BrickMeta M = load_meta(X.c.meta, b);
   bool act = (act_mask(M) >> L.m) & 1ull;
@@ -776,11 +785,11 @@ __device__ __forceinline__ void sweep_w_brick(const LevelViewT<V, CL, CI> &X,
   bstore<V>(X.w, L.m, b * 64u, x);
 }
 
-template <class V, class CL, class CI>
+template <class V, class CL, class CI, int CP = kCpolDefault>
 __global__ void __launch_bounds__(kBlock) k_T_sweep_w(LevelArgsT<V, CL, CI> A, int colour) {
   if (A.done && *A.done) return;
   const LaneC<V, CL> L = lane_consts<V, CL>();
-  const LevelViewT<V, CL, CI> X = level_view_T(A);
+  const LevelViewT<V, CL, CI, CP> X = level_view_T<CP>(A);
   const WaveLoop W = wave_loop(A.R.n());
   for (uint32_t i = W.first; i < W.end; i += W.step) {
     if (i < A.R.n_leaf) sweep_w_brick<false>(X, L, A.R.leaf_lo + i, colour);
@@ -793,8 +802,8 @@ __global__ void __launch_bounds__(kBlock) k_T_sweep_w(LevelArgsT<V, CL, CI> A, i
 // With next >= 0 the first step of the following half-sweep is taken too:
 // W2 = RHO / c on the active cells of colour next (own cells only, so no
 // other wave needs them during this launch), 0 elsewhere.
-template <bool INNER, class V, class CL, class CI>
-__device__ __forceinline__ void apply_T_brick(const LevelViewT<V, CL, CI> &X,
+template <bool INNER, class V, class CL, class CI, int CP>
+__device__ __forceinline__ void apply_T_brick(const LevelViewT<V, CL, CI, CP> &X,
                                               const LaneC<V, CL> &L, uint32_t b, int colour,
                                               int next) {
   const BrickMeta M = load_meta(X.c.meta, b);
@@ -810,12 +819,12 @@ __device__ __forceinline__ void apply_T_brick(const LevelViewT<V, CL, CI> &X,
   }
 }
 
-template <class V, class CL, class CI>
+template <class V, class CL, class CI, int CP = kCpolDefault>
 __global__ void __launch_bounds__(kBlock) k_T_apply(LevelArgsT<V, CL, CI> A, int colour,
                                                     int next) {
   if (A.done && *A.done) return;
   const LaneC<V, CL> L = lane_consts<V, CL>();
-  const LevelViewT<V, CL, CI> X = level_view_T(A);
+  const LevelViewT<V, CL, CI, CP> X = level_view_T<CP>(A);
   const WaveLoop W = wave_loop(A.R.n());
   for (uint32_t i = W.first; i < W.end; i += W.step) {
     if (i < A.R.n_leaf) apply_T_brick<false>(X, L, A.R.leaf_lo + i, colour, next);

@@ -105,6 +105,23 @@ inline unsigned stencil_grid(int64_t bricks) {
   if (waves_override()) return grid_waves(bricks, waves_override());
   return grid_waves(bricks, sizeof(V) == 8 ? kWavesPerXcd64 : kWavesPerXcd32);
 }
+// A stencil launch whose single-use streams (coefficients, plus faces,
+// right-hand side) and iterate together exceed the 256 MB Infinity Cache
+// gains nothing from caching those streams for the next launch, and they
+// only push the iterate's lines out of L2: such launches load them
+// non-temporal (kCpolStream).  Measured on the large workload: the finest
+// mixed half-sweep (about 415 MB) runs 11% faster that way, the next
+// level (about 140 MB, re-read from the Infinity Cache by the following
+// half-sweep) 20% slower.  MFMG_STREAM_BYTES (read once) overrides the
+// threshold, for tuning.
+inline double stream_threshold() {
+  static const double v = [] {
+    const char *e = std::getenv("MFMG_STREAM_BYTES");
+    double x = e ? std::atof(e) : -1.0;
+    return x >= 0 ? x : 256.0 * 1024 * 1024;
+  }();
+  return v;
+}
 inline unsigned grid_elems(int64_t n, int t) { return unsigned(std::max<int64_t>(1, (n + t - 1) / t)); }
 
 // grid of the Krylov kernels (grid-stride over leaf bricks, one partial sum
@@ -159,6 +176,8 @@ struct mfmg_hierarchy {
   DevBuf<double> pf64;     // plus-face coefficients, nb * 48 (FP64 cycle, composite operator)
   DevBuf<float> pf32;      // plus-face coefficients, nb * 48 (mixed cycle)
   double n_active = 0;     // active leaf cells
+  std::vector<char> stream_lv;  // per level: the cycle's stencils stream their coefficients
+  bool stream_composite = false;  // the same for the composite operator
   // work vectors (device order)
   DevBuf<double> U64, B64, S64;  // FP64 cycle: nb*64, nb*64, (nb-nlb)*64
   DevBuf<float> U32, B32, S32;   // mixed cycle
@@ -546,6 +565,20 @@ extern "C" mfmg_status mfmg_build_hierarchy(const mfmg_coeffs *co, const mfmg_mg
     int64_t na = 0;
     for (const BrickMeta &M : mh) na += __builtin_popcount(M.act[0]) + __builtin_popcount(M.act[1]);
     h->n_active = double(na);
+    {
+      // bytes one half-sweep of a level touches: iterate and right-hand
+      // side, four coefficients' worth of face data, the brick records
+      bool mixed = prm->precision == MFMG_MIXED;
+      double V = mixed ? 4.0 : 8.0, CL = mixed ? 4.0 : 8.0, CI = mixed ? 2.0 : 8.0;
+      h->stream_lv.assign(size_t(T.max_level) + 1, 0);
+      for (int l = kMinLevel; l <= T.max_level; ++l) {
+        const Range &R = D.range[l];
+        double ws = double(R.n_leaf) * (64 * (2 * V + 3.75 * CL) + 64) +
+                    double(R.n_inner) * (64 * (2 * V + 3.75 * CI) + 64);
+        h->stream_lv[size_t(l)] = ws > stream_threshold();
+      }
+      h->stream_composite = double(nlb) * (64 * (2 * 8.0 + 3.75 * 8.0) + 64) > stream_threshold();
+    }
     *out = h.release();
   } catch (const HipError &e) {
     return hip_fail(e);
@@ -633,10 +666,13 @@ struct Cycle {
     return A;
   }
 
-  void half_sweep(const LevelArgs<V, CL, CI> &A, int colour) const {
-    hipLaunchKernelGGL((k_smooth<V, CL, CI>), dim3(stencil_grid<V>(A.R.n())), dim3(kBlock), 0,
-                       s, A,
-                       colour);
+  bool stream(int l) const { return h->stream_lv[size_t(l)]; }
+  void half_sweep(int l, const LevelArgs<V, CL, CI> &A, int colour) const {
+    dim3 g(stencil_grid<V>(A.R.n()));
+    if (stream(l))
+      hipLaunchKernelGGL((k_smooth<V, CL, CI, kCpolStream>), g, dim3(kBlock), 0, s, A, colour);
+    else
+      hipLaunchKernelGGL((k_smooth<V, CL, CI>), g, dim3(kBlock), 0, s, A, colour);
   }
   void smooth(int l, int first, int nu, bool zero_start = false) const {
     auto A = args(l, false);
@@ -644,11 +680,16 @@ struct Cycle {
     for (int it = 0; it < nu; ++it)
       for (int c = 0; c < 2; ++c) {
         int colour = c == 0 ? first : 1 - first;
-        if (zero_start && it == 0 && c == 0)
-          hipLaunchKernelGGL((k_smooth_zero<V, CL, CI>), dim3(stencil_grid<V>(A.R.n())),
-                             dim3(kBlock), 0, s, A, colour);
-        else
-          half_sweep(A, colour);
+        dim3 g(stencil_grid<V>(A.R.n()));
+        if (zero_start && it == 0 && c == 0) {
+          if (stream(l))
+            hipLaunchKernelGGL((k_smooth_zero<V, CL, CI, kCpolStream>), g, dim3(kBlock), 0, s,
+                               A, colour);
+          else
+            hipLaunchKernelGGL((k_smooth_zero<V, CL, CI>), g, dim3(kBlock), 0, s, A, colour);
+        } else {
+          half_sweep(l, A, colour);
+        }
       }
   }
 
@@ -667,9 +708,12 @@ struct Cycle {
     smooth(l, 0, p.nu_pre, zero_start);
     auto A = args(l, false);
     V scale = V(p.beta_mg / p.alpha);
-    hipLaunchKernelGGL((k_restrict<V, CL, CI>), dim3(stencil_grid<V>(A.R.n())), dim3(kBlock),
-                       0, s,
-                       A, scale);
+    if (stream(l))
+      hipLaunchKernelGGL((k_restrict<V, CL, CI, kCpolStream>), dim3(stencil_grid<V>(A.R.n())),
+                         dim3(kBlock), 0, s, A, scale);
+    else
+      hipLaunchKernelGGL((k_restrict<V, CL, CI>), dim3(stencil_grid<V>(A.R.n())), dim3(kBlock),
+                         0, s, A, scale);
     auto C = args(l - 1, true);
     if (C.R.n())
       hipLaunchKernelGGL((k_fas_rhs<V, CL, CI>), dim3(stencil_grid<V>(C.R.n_inner)),
@@ -755,8 +799,12 @@ struct CycleT {
     auto A = args(l, 0);
     A.W = win;
     A.W2 = wout ? wout : win;
-    hipLaunchKernelGGL((k_T_apply<V, CL, CI>), dim3(stencil_grid<V>(A.R.n())), dim3(kBlock),
-                       0, s, A, colour, next);
+    if (h->stream_lv[size_t(l)])
+      hipLaunchKernelGGL((k_T_apply<V, CL, CI, kCpolStream>), dim3(stencil_grid<V>(A.R.n())),
+                         dim3(kBlock), 0, s, A, colour, next);
+    else
+      hipLaunchKernelGGL((k_T_apply<V, CL, CI>), dim3(stencil_grid<V>(A.R.n())), dim3(kBlock),
+                         0, s, A, colour, next);
     if (l > h->lc) {
       auto C = args(l - 1, 1);
       C.W = win;
@@ -775,8 +823,12 @@ struct CycleT {
     if (A.R.n() == 0 || nu == 0) return;
     if (!w_ready) {
       A.W = W2;
-      hipLaunchKernelGGL((k_T_sweep_w<V, CL, CI>), dim3(stencil_grid<V>(A.R.n())),
-                         dim3(kBlock), 0, s, A, first);
+      if (h->stream_lv[size_t(l)])
+        hipLaunchKernelGGL((k_T_sweep_w<V, CL, CI, kCpolStream>), dim3(stencil_grid<V>(A.R.n())),
+                           dim3(kBlock), 0, s, A, first);
+      else
+        hipLaunchKernelGGL((k_T_sweep_w<V, CL, CI>), dim3(stencil_grid<V>(A.R.n())),
+                           dim3(kBlock), 0, s, A, first);
     }
     V *buf[2] = {W2, W};
     for (int k = 0; k < 2 * nu; ++k) {
@@ -1000,8 +1052,11 @@ struct Krylov {
     if (trans)
       hipLaunchKernelGGL(k_pcg_ApT, dim3(GB), dim3(kBlock), 0, s, P, (const double *)h->pd.p,
                          h->Ap.p);
+    else if (h->stream_composite)
+      hipLaunchKernelGGL(k_pcg_Ap<kCpolStream>, dim3(GA), dim3(kBlock), 0, s, P,
+                         (const double *)h->pd.p, h->Ap.p);
     else
-      hipLaunchKernelGGL(k_pcg_Ap, dim3(GA), dim3(kBlock), 0, s, P, (const double *)h->pd.p,
+      hipLaunchKernelGGL(k_pcg_Ap<>, dim3(GA), dim3(kBlock), 0, s, P, (const double *)h->pd.p,
                          h->Ap.p);
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, P, int64_t(trans ? GB : GA),
                        int(kFinAlpha), 0, 0.0);
@@ -1426,13 +1481,13 @@ extern "C" mfmg_status mfmg_profile(mfmg_hierarchy *h, int what, int level, int 
         if (mixed) {
           Cycle<float, float, __half> c{h, h->coef32.p, h->coef16.p, h->pf32.p,
                                         h->U32.p, h->B32.p, h->S32.p, nullptr, s};
-          c.half_sweep(c.args(level, false), 0);
+          c.half_sweep(level, c.args(level, false), 0);
         } else {
           Cycle<double, double, double> c{h, h->coef64.p,
                                           h->coef64.p + int64_t(h->co->dt->nlb) * 256,
                                           h->pf64.p, h->U64.p, h->B64.p, h->S64.p,
                                           nullptr, s};
-          c.half_sweep(c.args(level, false), 0);
+          c.half_sweep(level, c.args(level, false), 0);
         }
       } else if (what == MFMG_PROFILE_CYCLE) {
         run_cycle(h, s, nullptr);

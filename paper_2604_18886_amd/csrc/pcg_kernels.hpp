@@ -112,9 +112,10 @@ __device__ __forceinline__ void average_up(double *__restrict__ X, const BrickMe
 // k, the sum of the fine sub-face coefficients over 2 (the coarse side of a
 // T-junction), and the fine side takes the ghost of Eq. (10).  It therefore
 // runs through stencil_sum, on the FP64 coefficient arrays.
-__device__ __forceinline__ LevelView<double, double, double> composite_view(const PcgArgs &P,
-                                                                            const double *X) {
-  LevelView<double, double, double> V;
+template <int CP = kCpolDefault>
+__device__ __forceinline__ LevelView<double, double, double, CP> composite_view(const PcgArgs &P,
+                                                                                const double *X) {
+  LevelView<double, double, double, CP> V;
   uint64_t nb = P.T.nb, nlb = P.T.nlb;
   V.u = make_rsrc(X, nb * 64 * sizeof(double));
   V.b = V.u;
@@ -129,7 +130,8 @@ __device__ __forceinline__ LevelView<double, double, double> composite_view(cons
 }
 
 // y = (A X)_m at the lane's cell of leaf brick b (0 on inactive cells); u = X_m.
-__device__ __forceinline__ double composite_row(const LevelView<double, double, double> &V,
+template <int CP>
+__device__ __forceinline__ double composite_row(const LevelView<double, double, double, CP> &V,
                                                 const LaneC<double, double> &L, uint32_t b,
                                                 double &u) {
   const BrickMeta M = load_meta(V.meta, b);
@@ -233,9 +235,10 @@ __global__ void __launch_bounds__(kBlock) k_pcg_p(PcgArgs P, const V *z, double 
 
 // Ap = A p over the leaf bricks (wave_loop grid); each workgroup stores its
 // partial (p, Ap), k_finish_alpha adds them in fixed order.
+template <int CP = kCpolDefault>
 __global__ void __launch_bounds__(kBlock) k_pcg_Ap(PcgArgs P, const double *p, double *Ap) {
   if (P.S->done) return;
-  const LevelView<double, double, double> V = composite_view(P, p);
+  const LevelView<double, double, double, CP> V = composite_view<CP>(P, p);
   const LaneC<double, double> L = lane_consts<double, double>();
   const __amdgpu_buffer_rsrc_t out = make_rsrc(Ap, uint64_t(P.T.nlb) * 64 * sizeof(double));
   const WaveLoop W = wave_loop(P.T.nlb);
