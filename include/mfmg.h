@@ -94,6 +94,23 @@ typedef struct {
  * Errors: INVALID_ARG (NULL, node_size != 4, bad levels or primitive kind). */
 mfmg_status mfmg_build_octree(const mfmg_refine_spec *spec, mfmg_octree **out);
 
+/* The same octree (same leaves, faces and orders, bit for bit) built on the
+ * device, for a tree that changes every time step (neighbour tables, then
+ * re-assembly and Algorithm 3 coarsening on the device).  Refinement by the
+ * predicates level by level, then the 2:1 balance as one pass from the
+ * finest level down (each node needs the level l-1 node that contains its
+ * face neighbour; a missing one is made by splitting its parent), over
+ * dense per-level tables of 8^(l-2) bytes and 8^(l-2) int32 (so about
+ * 4.4 GB of temporary device memory at max_level 12, 70 MB at 10), freed
+ * before return.  Work is queued on stream; the call returns after the
+ * stream has drained.  The octree holds device tables only: it serves
+ * everything below except mfmg_hierarchy_level_bricks/_coeffs, and its
+ * host leaves/faces are device outputs copied back (null stream).
+ * Errors: INVALID_ARG (as mfmg_build_octree), OOM, HIP, TOPOLOGY (an
+ * internal invariant failed). */
+mfmg_status mfmg_build_octree_device(const mfmg_refine_spec *spec, void *stream,
+                                     mfmg_octree **out);
+
 /* Sizes of the octree: leaf cells, faces, leaf bricks (any output may be
  * NULL).  Host only. */
 mfmg_status mfmg_octree_info(const mfmg_octree *tree, int64_t *n_leaves,
@@ -111,6 +128,16 @@ mfmg_status mfmg_octree_leaves(const mfmg_octree *tree, uint8_t *level,
  *   kind:  0 wall, 1 same level, 2 T-junction (owner finer than other). */
 mfmg_status mfmg_octree_faces(const mfmg_octree *tree, int64_t *owner,
                               int8_t *dir, int64_t *other, int8_t *kind);
+
+/* mfmg_octree_leaves and mfmg_octree_faces into device buffers of the same
+ * sizes, written by kernels queued on stream (not waited for).  For a
+ * host-built octree the first call (or the first assembly) uploads its
+ * device tables, which the octree keeps. */
+mfmg_status mfmg_octree_leaves_device(const mfmg_octree *tree, uint8_t *level,
+                                      int32_t *ijk, void *stream);
+mfmg_status mfmg_octree_faces_device(const mfmg_octree *tree, int64_t *owner,
+                                     int8_t *dir, int64_t *other, int8_t *kind,
+                                     void *stream);
 
 void mfmg_destroy_octree(mfmg_octree *tree);
 

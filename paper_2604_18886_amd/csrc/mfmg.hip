@@ -13,6 +13,7 @@
 
 #include "../../include/mfmg.h"
 #include "kernels.hpp"
+#include "octree_kernels.hpp"
 #include "pcg_kernels.hpp"
 #include "topology.hpp"
 
@@ -136,17 +137,13 @@ inline unsigned grid_reduce(int64_t bricks) {
 // --------------------------------------------------------------------------
 // objects
 // --------------------------------------------------------------------------
-struct mfmg_octree {
-  Topology topo;
-};
-
 // Device view of the topology.  Device brick ids are level-major (leaf bricks
 // by descending level then Morton order; inner bricks likewise); perm maps a
-// host brick id (canonical leaf order, then inner bricks) to its device id.
+// host brick id (canonical leaf order, then inner bricks) to its device id
+// (empty for an octree built on the device).
 struct DeviceTopology {
   std::vector<int32_t> perm;          // host brick -> device brick
-  std::vector<BrickMeta> meta_host;   // device order, act = 0
-  DevBuf<BrickMeta> meta;
+  DevBuf<BrickMeta> meta;             // act = 0
   DevBuf<int32_t> child;              // 8 per device brick
   DevBuf<int64_t> fbase;              // per device leaf cell
   DevBuf<uint8_t> fmask;              // per device leaf cell
@@ -155,9 +152,19 @@ struct DeviceTopology {
   uint32_t nlb = 0, nb = 0;
 };
 
+// An octree built on the host keeps its host topology (and makes its device
+// tables at first use); one built on the device has only the device tables.
+struct mfmg_octree {
+  Topology topo;  // host-built octrees only
+  bool on_host = true;
+  int min_level = 0, max_level = 0;
+  int64_t nlb = 0, nb = 0, n_faces = 0, n_tplus = 0;
+  mutable std::shared_ptr<DeviceTopology> dt;
+};
+
 struct mfmg_coeffs {
   const mfmg_octree *tree = nullptr;
-  std::unique_ptr<DeviceTopology> dt;
+  std::shared_ptr<DeviceTopology> dt;
   DevBuf<double> coef;  // nlb * 256, FP64 leaf coefficients (device order)
   DevBuf<double> tc;    // n_tplus * 48
   mfmg_bc bc{};
@@ -225,11 +232,10 @@ extern "C" const char *mfmg_last_error(void) { return g_err.c_str(); }
 // --------------------------------------------------------------------------
 // octree
 // --------------------------------------------------------------------------
-extern "C" mfmg_status mfmg_build_octree(const mfmg_refine_spec *spec, mfmg_octree **out) {
-  if (!spec || !out) return fail(MFMG_ERR_INVALID_ARG, "NULL argument");
+static mfmg_status convert_prims(const mfmg_refine_spec *spec, std::vector<Prim> &prims) {
   if (spec->n_prims < 0 || (spec->n_prims > 0 && !spec->prims))
     return fail(MFMG_ERR_INVALID_ARG, "bad primitive list");
-  std::vector<Prim> prims(spec->n_prims);
+  prims.assign(size_t(spec->n_prims), Prim{});
   for (int i = 0; i < spec->n_prims; ++i) {
     const mfmg_prim &p = spec->prims[i];
     Prim &q = prims[i];
@@ -243,6 +249,14 @@ extern "C" mfmg_status mfmg_build_octree(const mfmg_refine_spec *spec, mfmg_octr
     q.band = p.band;
     if (!(p.band >= 0.0)) return fail(MFMG_ERR_INVALID_ARG, "negative band");
   }
+  return MFMG_OK;
+}
+
+extern "C" mfmg_status mfmg_build_octree(const mfmg_refine_spec *spec, mfmg_octree **out) {
+  if (!spec || !out) return fail(MFMG_ERR_INVALID_ARG, "NULL argument");
+  std::vector<Prim> prims;
+  mfmg_status pst = convert_prims(spec, prims);
+  if (pst != MFMG_OK) return pst;
   std::unique_ptr<mfmg_octree> t(new (std::nothrow) mfmg_octree());
   if (!t) return fail(MFMG_ERR_OOM, "host allocation failed");
   std::string err;
@@ -255,6 +269,13 @@ extern "C" mfmg_status mfmg_build_octree(const mfmg_refine_spec *spec, mfmg_octr
     return fail(err.find("balanced") != std::string::npos ? MFMG_ERR_TOPOLOGY
                                                           : MFMG_ERR_INVALID_ARG,
                 err);
+  t->on_host = true;
+  t->min_level = t->topo.min_level;
+  t->max_level = t->topo.max_level;
+  t->nlb = t->topo.n_leaf_bricks;
+  t->nb = t->topo.n_bricks;
+  t->n_faces = t->topo.n_faces;
+  t->n_tplus = t->topo.n_tplus;
   *out = t.release();
   return MFMG_OK;
 }
@@ -262,14 +283,19 @@ extern "C" mfmg_status mfmg_build_octree(const mfmg_refine_spec *spec, mfmg_octr
 extern "C" mfmg_status mfmg_octree_info(const mfmg_octree *t, int64_t *n_leaves,
                                         int64_t *n_faces, int64_t *n_leaf_bricks) {
   if (!t) return fail(MFMG_ERR_INVALID_ARG, "NULL octree");
-  if (n_leaves) *n_leaves = t->topo.n_leaves();
-  if (n_faces) *n_faces = t->topo.n_faces;
-  if (n_leaf_bricks) *n_leaf_bricks = t->topo.n_leaf_bricks;
+  if (n_leaves) *n_leaves = t->nlb * kCells;
+  if (n_faces) *n_faces = t->n_faces;
+  if (n_leaf_bricks) *n_leaf_bricks = t->nlb;
   return MFMG_OK;
 }
 
+static mfmg_status leaves_from_device(const mfmg_octree *t, uint8_t *level, int32_t *ijk);
+static mfmg_status faces_from_device(const mfmg_octree *t, int64_t *owner, int8_t *dir,
+                                     int64_t *other, int8_t *kind);
+
 extern "C" mfmg_status mfmg_octree_leaves(const mfmg_octree *t, uint8_t *level, int32_t *ijk) {
   if (!t || !level || !ijk) return fail(MFMG_ERR_INVALID_ARG, "NULL argument");
+  if (!t->on_host) return leaves_from_device(t, level, ijk);
   const Topology &T = t->topo;
   for (int64_t b = 0; b < T.n_leaf_bricks; ++b)
     for (int m = 0; m < kCells; ++m) {
@@ -288,6 +314,7 @@ extern "C" mfmg_status mfmg_octree_faces(const mfmg_octree *t, int64_t *owner, i
                                          int64_t *other, int8_t *kind) {
   if (!t || !owner || !dir || !other || !kind)
     return fail(MFMG_ERR_INVALID_ARG, "NULL argument");
+  if (!t->on_host) return faces_from_device(t, owner, dir, other, kind);
   const Topology &T = t->topo;
   for (int64_t b = 0; b < T.n_leaf_bricks; ++b)
     for (int m = 0; m < kCells; ++m) {
@@ -339,10 +366,10 @@ static void build_device_topology(const Topology &T, DeviceTopology &D, hipStrea
       D.range[l].inner_lo = uint32_t(T.level_inner[l].front());
       D.range[l].n_inner = uint32_t(T.level_inner[l].size());
     }
-  D.meta_host.assign(nb, BrickMeta{});
+  std::vector<BrickMeta> meta_host(nb, BrickMeta{});
   std::vector<int32_t> child(8 * nb, -1);
   for (int64_t b = 0; b < nb; ++b) {
-    BrickMeta &M = D.meta_host[D.perm[b]];
+    BrickMeta &M = meta_host[D.perm[b]];
     std::memset(&M, 0, sizeof(M));
     M.flags = 0;
     for (int d = 0; d < 6; ++d) {
@@ -374,7 +401,7 @@ static void build_device_topology(const Topology &T, DeviceTopology &D, hipStrea
       fbase[int64_t(D.perm[b]) * kCells + m] = T.cell_fbase[b * kCells + m];
       fmask[int64_t(D.perm[b]) * kCells + m] = T.cell_fmask[b * kCells + m];
     }
-  D.meta.upload(D.meta_host, s);
+  D.meta.upload(meta_host, s);
   D.child.upload(child, s);
   D.fbase.upload(fbase, s);
   D.fmask.upload(fmask, s);
@@ -391,6 +418,300 @@ static Topo make_topo(const DeviceTopology &D, const BrickMeta *meta) {
   return t;
 }
 
+// Device tables of an octree: built with it on the device, or made from the
+// host topology at first use (not thread-safe for one octree).
+static std::shared_ptr<DeviceTopology> device_topology(const mfmg_octree *t, hipStream_t s) {
+  if (!t->dt) {
+    std::shared_ptr<DeviceTopology> d(new DeviceTopology());
+    build_device_topology(t->topo, *d, s);
+    t->dt = d;
+  }
+  return t->dt;
+}
+
+// exclusive scan of x[0, n) in place on stream s; *total (device) = sum
+static void scan_exclusive(int64_t *x, int64_t n, int64_t *total, hipStream_t s) {
+  int64_t tiles = std::max<int64_t>(1, (n + kScanTile - 1) / kScanTile);
+  DevBuf<int64_t> t;
+  t.alloc(size_t(tiles));
+  hipLaunchKernelGGL(k_scan_tiles, dim3(unsigned(tiles)), dim3(256), 0, s, x, n, t.p);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, t.p, tiles, total);
+  hipLaunchKernelGGL(k_scan_add, dim3(unsigned(tiles)), dim3(256), 0, s, x, n,
+                     (const int64_t *)t.p);
+  HIP_CHECK(hipStreamSynchronize(s));  // t is freed on return
+}
+
+static unsigned key_grid(uint64_t nk) {
+  return unsigned(std::min<uint64_t>((nk + 255) / 256, 65535));
+}
+
+// The octree of the spec built on the device (see octree_kernels.hpp);
+// returns "" or an error message.
+static std::string build_octree_device(const mfmg_refine_spec *spec,
+                                       const std::vector<Prim> &prims, hipStream_t s,
+                                       mfmg_octree &t) {
+  if (spec->node_size != kBrick) return "node_size must be 4";
+  int lmin = spec->min_level, lmax = spec->max_level;
+  if (lmin < kMinLevel || lmax > kMaxLevel || lmin > lmax)
+    return "levels out of range (2 <= min_level <= max_level <= 12)";
+  for (const Prim &p : prims)
+    if (p.kind != 0 && p.kind != 1) return "unknown primitive kind";
+  OctTables T;
+  T.min_level = lmin;
+  T.max_level = lmax;
+  uint64_t ns = 0, ni = 0;
+  for (int l = 0; l < kOctLevels; ++l) T.split_off[l] = T.id_off[l] = 0;
+  for (int l = kMinLevel; l <= lmax; ++l) {
+    if (l < lmax) {
+      T.split_off[l] = ns;
+      ns += oct_keys(l);
+    }
+    T.id_off[l] = ni;
+    ni += oct_keys(l);
+  }
+  DevBuf<uint8_t> split;
+  DevBuf<int32_t> id;
+  split.alloc(std::max<uint64_t>(ns, 1));
+  id.alloc(ni);
+  T.split = split.p;
+  T.id = id.p;
+  DevBuf<Prim> dprims;
+  dprims.upload(prims, s);
+  // refinement by the predicates, then 2:1 balance from the finest level down
+  for (int l = kMinLevel; l < lmax; ++l)
+    hipLaunchKernelGGL(k_oct_refine, dim3(key_grid(oct_keys(l))), dim3(256), 0, s, T, l,
+                       (const Prim *)dprims.p, int(prims.size()));
+  for (int l = lmax; l >= lmin + 2; --l)
+    hipLaunchKernelGGL(k_oct_balance, dim3(key_grid(oct_keys(l))), dim3(256), 0, s, T, l);
+  // leaf and inner counts per level
+  uint64_t boff[kOctLevels + 1] = {0};
+  for (int l = kMinLevel; l <= lmax; ++l)
+    boff[l + 1] = boff[l] + (oct_keys(l) + kOctTile - 1) / kOctTile;
+  for (int l = 0; l < kMinLevel; ++l) boff[l + 1] = 0;
+  DevBuf<uint32_t> cnt, tot;
+  cnt.alloc(2 * boff[lmax + 1]);
+  tot.alloc(2 * kOctLevels);
+  for (int l = kMinLevel; l <= lmax; ++l) {
+    uint64_t nblk = boff[l + 1] - boff[l];
+    hipLaunchKernelGGL(k_oct_count, dim3(unsigned(nblk)), dim3(kOctThreads), 0, s, T, l,
+                       cnt.p + 2 * boff[l]);
+    hipLaunchKernelGGL(k_oct_scan_pairs, dim3(1), dim3(1024), 0, s, cnt.p + 2 * boff[l], nblk,
+                       tot.p + 2 * l);
+  }
+  std::vector<uint32_t> th(2 * kOctLevels, 0);
+  HIP_CHECK(hipMemcpyAsync(th.data() + 2 * kMinLevel, tot.p + 2 * kMinLevel,
+                           2 * (lmax + 1 - kMinLevel) * sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  // device ids: leaves finest level first, then inner bricks finest first
+  OctLevels LV;
+  uint32_t inner_lo[kOctLevels] = {0};
+  for (int l = 0; l < kOctLevels; ++l) LV.leaf_lo[l] = LV.n_leaf[l] = 0;
+  uint64_t nlb = 0;
+  for (int l = lmax; l >= kMinLevel; --l) {
+    LV.leaf_lo[l] = uint32_t(nlb);
+    LV.n_leaf[l] = th[2 * l];
+    nlb += th[2 * l];
+  }
+  uint64_t nb = nlb;
+  for (int l = lmax; l >= kMinLevel; --l) {
+    inner_lo[l] = uint32_t(nb);
+    nb += th[2 * l + 1];
+  }
+  if (nb >= (uint64_t(1) << 31) / kCells) return "octree too large";
+  DevBuf<uint32_t> bkey;
+  DevBuf<int8_t> blev;
+  bkey.alloc(nb);
+  blev.alloc(nb);
+  for (int l = kMinLevel; l <= lmax; ++l)
+    hipLaunchKernelGGL(k_oct_assign, dim3(unsigned(boff[l + 1] - boff[l])), dim3(kOctThreads),
+                       0, s, T, l, (const uint32_t *)cnt.p + 2 * boff[l], LV.leaf_lo[l],
+                       inner_lo[l], bkey.p, blev.p);
+  std::shared_ptr<DeviceTopology> dp(new DeviceTopology());
+  DeviceTopology &D = *dp;
+  D.nlb = uint32_t(nlb);
+  D.nb = uint32_t(nb);
+  D.range.assign(lmax + 1, Range{0, 0, 0, 0});
+  for (int l = kMinLevel; l <= lmax; ++l)
+    D.range[l] = Range{th[2 * l] ? LV.leaf_lo[l] : 0u, th[2 * l],
+                       th[2 * l + 1] ? inner_lo[l] : 0u, th[2 * l + 1]};
+  D.meta.alloc(nb);
+  D.child.alloc(8 * nb);
+  D.canon.alloc(nlb);
+  D.fbase.alloc(nlb * kCells);
+  D.fmask.alloc(nlb * kCells);
+  DevBuf<int32_t> inv;
+  DevBuf<int> err;
+  inv.alloc(nlb);
+  err.alloc(1);
+  HIP_CHECK(hipMemsetAsync(err.p, 0, sizeof(int), s));
+  HIP_CHECK(hipMemsetAsync(inv.p, 0xff, size_t(nlb) * sizeof(int32_t), s));
+  int eh = 0;
+  if (nlb) {
+    hipLaunchKernelGGL(k_oct_canon, dim3(grid_elems(int64_t(nlb), 256)), dim3(256), 0, s, T,
+                       LV, uint32_t(nlb), (const uint32_t *)bkey.p, (const int8_t *)blev.p,
+                       D.canon.p, inv.p, err.p);
+    hipLaunchKernelGGL(k_oct_check_perm, dim3(grid_elems(int64_t(nlb), 256)), dim3(256), 0, s,
+                       (const int32_t *)inv.p, uint32_t(nlb), err.p);
+    HIP_CHECK(hipMemcpyAsync(&eh, err.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    if (eh) return "canonical leaf order is not a permutation";
+  }
+  hipLaunchKernelGGL(k_oct_meta, dim3(grid_elems(int64_t(nb), 256)), dim3(256), 0, s, T,
+                     uint32_t(nlb), uint32_t(nb), (const uint32_t *)bkey.p,
+                     (const int8_t *)blev.p, D.meta.p, D.child.p, err.p);
+  // plus-side T-face slots and face numbering, both in canonical order
+  DevBuf<int64_t> work, totals;
+  work.alloc(std::max<uint64_t>(nlb, 1));
+  totals.alloc(2);
+  hipLaunchKernelGGL(k_oct_tflag, dim3(grid_elems(int64_t(nlb), 256)), dim3(256), 0, s,
+                     (const BrickMeta *)D.meta.p, (const int32_t *)inv.p, uint32_t(nlb), work.p);
+  scan_exclusive(work.p, int64_t(nlb), totals.p, s);
+  hipLaunchKernelGGL(k_oct_tplus, dim3(grid_elems(int64_t(nlb), 256)), dim3(256), 0, s,
+                     D.meta.p, (const int32_t *)inv.p, uint32_t(nlb), (const int64_t *)work.p);
+  hipLaunchKernelGGL(k_oct_fmask, dim3(grid_for(int64_t(nlb))), dim3(kBlock), 0, s,
+                     (const BrickMeta *)D.meta.p, (const int32_t *)D.canon.p, uint32_t(nlb),
+                     D.fmask.p, work.p);
+  scan_exclusive(work.p, int64_t(nlb), totals.p + 1, s);
+  hipLaunchKernelGGL(k_oct_fbase, dim3(grid_for(int64_t(nlb))), dim3(kBlock), 0, s,
+                     (const uint8_t *)D.fmask.p, (const int32_t *)D.canon.p, uint32_t(nlb),
+                     (const int64_t *)work.p, D.fbase.p);
+  int64_t th2[2];
+  HIP_CHECK(hipMemcpyAsync(th2, totals.p, sizeof(th2), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(&eh, err.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipGetLastError());
+  HIP_CHECK(hipStreamSynchronize(s));
+  if (eh) return "octree is not 2:1 balanced";
+  t.on_host = false;
+  t.min_level = lmin;
+  t.max_level = lmax;
+  t.nlb = int64_t(nlb);
+  t.nb = int64_t(nb);
+  t.n_tplus = th2[0];
+  t.n_faces = th2[1];
+  t.dt = dp;
+  return "";
+}
+
+static mfmg_status leaves_to(const mfmg_octree *t, uint8_t *level, int32_t *ijk,
+                             hipStream_t s) {
+  std::shared_ptr<DeviceTopology> D = device_topology(t, s);
+  if (D->nlb)
+    hipLaunchKernelGGL(k_oct_leaves, dim3(grid_for(D->nlb)), dim3(kBlock), 0, s,
+                       (const BrickMeta *)D->meta.p, (const int32_t *)D->canon.p, D->nlb, level,
+                       ijk);
+  HIP_CHECK(hipGetLastError());
+  return MFMG_OK;
+}
+
+static mfmg_status faces_to(const mfmg_octree *t, int64_t *owner, int8_t *dir, int64_t *other,
+                            int8_t *kind, hipStream_t s) {
+  std::shared_ptr<DeviceTopology> D = device_topology(t, s);
+  if (D->nlb)
+    hipLaunchKernelGGL(k_oct_faces, dim3(grid_for(D->nlb)), dim3(kBlock), 0, s,
+                       (const BrickMeta *)D->meta.p, (const int32_t *)D->canon.p,
+                       (const int64_t *)D->fbase.p, (const uint8_t *)D->fmask.p, D->nlb, owner,
+                       dir, other, kind);
+  HIP_CHECK(hipGetLastError());
+  return MFMG_OK;
+}
+
+extern "C" mfmg_status mfmg_build_octree_device(const mfmg_refine_spec *spec, void *stream,
+                                                mfmg_octree **out) {
+  if (!spec || !out) return fail(MFMG_ERR_INVALID_ARG, "NULL argument");
+  std::vector<Prim> prims;
+  mfmg_status st = convert_prims(spec, prims);
+  if (st != MFMG_OK) return st;
+  std::unique_ptr<mfmg_octree> t(new (std::nothrow) mfmg_octree());
+  if (!t) return fail(MFMG_ERR_OOM, "host allocation failed");
+  std::string err;
+  try {
+    err = build_octree_device(spec, prims, (hipStream_t)stream, *t);
+  } catch (const HipError &e) {
+    return hip_fail(e);
+  } catch (const std::bad_alloc &) {
+    return fail(MFMG_ERR_OOM, "host allocation failed");
+  }
+  if (!err.empty())
+    return fail(err.find("balanced") != std::string::npos ? MFMG_ERR_TOPOLOGY
+                                                          : MFMG_ERR_INVALID_ARG,
+                err);
+  *out = t.release();
+  return MFMG_OK;
+}
+
+extern "C" mfmg_status mfmg_octree_leaves_device(const mfmg_octree *t, uint8_t *level,
+                                                 int32_t *ijk, void *stream) {
+  if (!t || !level || !ijk) return fail(MFMG_ERR_INVALID_ARG, "NULL argument");
+  try {
+    return leaves_to(t, level, ijk, (hipStream_t)stream);
+  } catch (const HipError &e) {
+    return hip_fail(e);
+  } catch (const std::bad_alloc &) {
+    return fail(MFMG_ERR_OOM, "host allocation failed");
+  }
+}
+
+extern "C" mfmg_status mfmg_octree_faces_device(const mfmg_octree *t, int64_t *owner,
+                                                int8_t *dir, int64_t *other, int8_t *kind,
+                                                void *stream) {
+  if (!t || !owner || !dir || !other || !kind)
+    return fail(MFMG_ERR_INVALID_ARG, "NULL argument");
+  try {
+    return faces_to(t, owner, dir, other, kind, (hipStream_t)stream);
+  } catch (const HipError &e) {
+    return hip_fail(e);
+  } catch (const std::bad_alloc &) {
+    return fail(MFMG_ERR_OOM, "host allocation failed");
+  }
+}
+
+// host outputs of a device-built octree: the device outputs, copied back
+static mfmg_status leaves_from_device(const mfmg_octree *t, uint8_t *level, int32_t *ijk) {
+  try {
+    hipStream_t s = nullptr;
+    int64_t n = t->nlb * kCells;
+    DevBuf<uint8_t> lv;
+    DevBuf<int32_t> c;
+    lv.alloc(size_t(std::max<int64_t>(n, 1)));
+    c.alloc(size_t(std::max<int64_t>(3 * n, 1)));
+    mfmg_status st = leaves_to(t, lv.p, c.p, s);
+    if (st != MFMG_OK) return st;
+    HIP_CHECK(hipMemcpyAsync(level, lv.p, size_t(n), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipMemcpyAsync(ijk, c.p, size_t(3 * n) * sizeof(int32_t), hipMemcpyDeviceToHost,
+                             s));
+    HIP_CHECK(hipStreamSynchronize(s));
+  } catch (const HipError &e) {
+    return hip_fail(e);
+  }
+  return MFMG_OK;
+}
+
+static mfmg_status faces_from_device(const mfmg_octree *t, int64_t *owner, int8_t *dir,
+                                     int64_t *other, int8_t *kind) {
+  try {
+    hipStream_t s = nullptr;
+    size_t n = size_t(std::max<int64_t>(t->n_faces, 1));
+    DevBuf<int64_t> ow, ot;
+    DevBuf<int8_t> di, ki;
+    ow.alloc(n);
+    ot.alloc(n);
+    di.alloc(n);
+    ki.alloc(n);
+    mfmg_status st = faces_to(t, ow.p, di.p, ot.p, ki.p, s);
+    if (st != MFMG_OK) return st;
+    size_t nf = size_t(t->n_faces);
+    HIP_CHECK(hipMemcpyAsync(owner, ow.p, nf * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipMemcpyAsync(other, ot.p, nf * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipMemcpyAsync(dir, di.p, nf, hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipMemcpyAsync(kind, ki.p, nf, hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+  } catch (const HipError &e) {
+    return hip_fail(e);
+  }
+  return MFMG_OK;
+}
+
 extern "C" mfmg_status mfmg_assemble_coeffs(const mfmg_octree *tree, const double *face_beta,
                                             const mfmg_bc *bc, void *stream,
                                             mfmg_coeffs **out) {
@@ -401,16 +722,14 @@ extern "C" mfmg_status mfmg_assemble_coeffs(const mfmg_octree *tree, const doubl
   if (!(bc->theta > 0.0 && bc->theta <= 1.0))
     return fail(MFMG_ERR_INVALID_ARG, "theta must be in (0, 1]");
   hipStream_t s = (hipStream_t)stream;
-  const Topology &T = tree->topo;
   try {
     std::unique_ptr<mfmg_coeffs> co(new mfmg_coeffs());
     co->tree = tree;
     co->bc = *bc;
     for (int d = 0; d < 6; ++d) co->has_dirichlet |= bc->bc[d] == MFMG_DIRICHLET;
-    co->dt.reset(new DeviceTopology());
-    build_device_topology(T, *co->dt, s);
-    co->coef.alloc(size_t(T.n_leaf_bricks) * 256);
-    co->tc.alloc(size_t(T.n_tplus) * 48 + 1);
+    co->dt = device_topology(tree, s);
+    co->coef.alloc(size_t(tree->nlb) * 256);
+    co->tc.alloc(size_t(tree->n_tplus) * 48 + 1);
     AssembleArgs A;
     A.T = make_topo(*co->dt, co->dt->meta.p);
     A.fbase = co->dt->fbase.p;
@@ -420,7 +739,8 @@ extern "C" mfmg_status mfmg_assemble_coeffs(const mfmg_octree *tree, const doubl
     A.theta = bc->theta;
     A.coef = co->coef.p;
     A.tc = co->tc.p;
-    hipLaunchKernelGGL(k_assemble, dim3(grid_for(T.n_leaf_bricks)), dim3(kBlock), 0, s, A);
+    if (tree->nlb)
+      hipLaunchKernelGGL(k_assemble, dim3(grid_for(tree->nlb)), dim3(kBlock), 0, s, A);
     HIP_CHECK(hipGetLastError());
     HIP_CHECK(hipStreamSynchronize(s));
     *out = co.release();
@@ -466,7 +786,7 @@ extern "C" void mfmg_destroy_coeffs(mfmg_coeffs *co) { delete co; }
 extern "C" mfmg_status mfmg_build_hierarchy(const mfmg_coeffs *co, const mfmg_mg_params *prm,
                                             void *stream, mfmg_hierarchy **out) {
   if (!co || !prm || !out) return fail(MFMG_ERR_INVALID_ARG, "NULL argument");
-  const Topology &T = co->tree->topo;
+  const mfmg_octree &T = *co->tree;
   if (prm->coarsest_level < kMinLevel || prm->coarsest_level > T.min_level)
     return fail(MFMG_ERR_INVALID_ARG, "coarsest_level must be in [2, min_level]");
   if (prm->nu_pre < 0 || prm->nu_post < 0 || prm->nu_coarse < 0 || prm->mu < 1 || prm->mu > 4)
@@ -500,7 +820,9 @@ extern "C" mfmg_status mfmg_build_hierarchy(const mfmg_coeffs *co, const mfmg_mg
     for (int l = kMinLevel; l <= T.max_level; ++l)
       if (D.range[l].n() > 0) h->L = l;
     int64_t nb = D.nb, nlb = D.nlb, N = nlb * 64;
-    h->meta.upload(D.meta_host, s);
+    h->meta.alloc(D.nb);
+    HIP_CHECK(hipMemcpyAsync(h->meta.p, D.meta.p, size_t(D.nb) * sizeof(BrickMeta),
+                             hipMemcpyDeviceToDevice, s));
     h->coef64.alloc(size_t(nb) * 256);
     HIP_CHECK(hipMemcpyAsync(h->coef64.p, co->coef.p, size_t(nlb) * 256 * sizeof(double),
                              hipMemcpyDeviceToDevice, s));
@@ -592,6 +914,8 @@ extern "C" mfmg_status mfmg_hierarchy_level_bricks(const mfmg_hierarchy *h, int 
                                                    int64_t *count, int32_t *coords,
                                                    uint8_t *is_leaf) {
   if (!h || !count) return fail(MFMG_ERR_INVALID_ARG, "NULL argument");
+  if (!h->co->tree->on_host)
+    return fail(MFMG_ERR_INVALID_ARG, "needs an octree built on the host");
   const Topology &T = h->co->tree->topo;
   if (level < kMinLevel || level > T.max_level) return fail(MFMG_ERR_INVALID_ARG, "bad level");
   const auto &lst = T.level_bricks[level];
@@ -608,6 +932,8 @@ extern "C" mfmg_status mfmg_hierarchy_level_bricks(const mfmg_hierarchy *h, int 
 extern "C" mfmg_status mfmg_hierarchy_level_coeffs(const mfmg_hierarchy *h, int level,
                                                    double *out, void *stream) {
   if (!h || !out) return fail(MFMG_ERR_INVALID_ARG, "NULL argument");
+  if (!h->co->tree->on_host)
+    return fail(MFMG_ERR_INVALID_ARG, "needs an octree built on the host");
   const Topology &T = h->co->tree->topo;
   if (level < kMinLevel || level > T.max_level) return fail(MFMG_ERR_INVALID_ARG, "bad level");
   hipStream_t s = (hipStream_t)stream;
@@ -1297,7 +1623,7 @@ extern "C" mfmg_status mfmg_pcg_solve_adjoint(mfmg_hierarchy *h, const double *p
   bool ns = sp->null_space == 1 || (sp->null_space == -1 && !h->co->has_dirichlet);
   if (sp->warm_start) return fail(MFMG_ERR_INVALID_ARG, "the adjoint solve starts from zero");
   hipStream_t s = (hipStream_t)stream;
-  const Topology &T = h->co->tree->topo;
+  const mfmg_octree &T = *h->co->tree;
   const DeviceTopology &D = *h->co->dt;
   mfmg_status st = MFMG_OK;
   try {
@@ -1308,31 +1634,21 @@ extern "C" mfmg_status mfmg_pcg_solve_adjoint(mfmg_hierarchy *h, const double *p
     if (!h->rA.p) h->rA.alloc(size_t(D.nlb) * 64);
     if (!h->f_owner.p) {
       // canonical face list and per-brick tables for the gradient
-      int64_t nf = T.n_faces;
-      std::vector<int64_t> owner(nf), other(nf);
-      std::vector<int8_t> dir(nf), kind(nf), lvl(T.n_leaf_bricks);
-      for (int64_t b = 0; b < T.n_leaf_bricks; ++b) {
-        lvl[b] = T.level[b];
-        for (int m = 0; m < kCells; ++m) {
-          int64_t c = b * kCells + m;
-          int64_t f = T.cell_fbase[c];
-          for (int d = 0; d < 6; ++d) {
-            if (!((T.cell_fmask[c] >> d) & 1)) continue;
-            int64_t o;
-            int k = T.cell_neighbour(b, m, d, &o);
-            owner[f] = c;
-            dir[f] = int8_t(d);
-            other[f] = o;
-            kind[f] = int8_t(k);
-            ++f;
-          }
-        }
+      size_t nf = size_t(std::max<int64_t>(T.n_faces, 1));
+      h->f_owner.alloc(nf);
+      h->f_other.alloc(nf);
+      h->f_dir.alloc(nf);
+      h->f_kind.alloc(nf);
+      h->leaf_level.alloc(size_t(D.nlb));
+      if (D.nlb) {
+        hipLaunchKernelGGL(k_oct_faces, dim3(grid_for(D.nlb)), dim3(kBlock), 0, s,
+                           (const BrickMeta *)D.meta.p, (const int32_t *)D.canon.p,
+                           (const int64_t *)D.fbase.p, (const uint8_t *)D.fmask.p, D.nlb,
+                           h->f_owner.p, h->f_dir.p, h->f_other.p, h->f_kind.p);
+        hipLaunchKernelGGL(k_oct_canon_level, dim3(grid_elems(D.nlb, 256)), dim3(256), 0, s,
+                           (const BrickMeta *)D.meta.p, (const int32_t *)D.canon.p, D.nlb,
+                           h->leaf_level.p);
       }
-      h->f_owner.upload(owner, s);
-      h->f_other.upload(other, s);
-      h->f_dir.upload(dir, s);
-      h->f_kind.upload(kind, s);
-      h->leaf_level.upload(lvl, s);
       h->canon_act.alloc(size_t(D.nlb));
       hipLaunchKernelGGL(k_canonical_act, dim3(grid_elems(D.nlb, 256)), dim3(256), 0, s,
                          (const BrickMeta *)h->meta.p, (const int32_t *)D.canon.p, D.nlb,

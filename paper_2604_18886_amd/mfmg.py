@@ -76,9 +76,13 @@ _I64P = ctypes.POINTER(ctypes.c_int64)
 SIGNATURES = {
     "mfmg_last_error": (ctypes.c_char_p, []),
     "mfmg_build_octree": (ctypes.c_int, [ctypes.POINTER(_Spec), ctypes.POINTER(_VP)]),
+    "mfmg_build_octree_device": (ctypes.c_int, [ctypes.POINTER(_Spec), _VP,
+                                                ctypes.POINTER(_VP)]),
     "mfmg_octree_info": (ctypes.c_int, [_VP, _I64P, _I64P, _I64P]),
     "mfmg_octree_leaves": (ctypes.c_int, [_VP, _VP, _VP]),
     "mfmg_octree_faces": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "mfmg_octree_leaves_device": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "mfmg_octree_faces_device": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "mfmg_destroy_octree": (None, [_VP]),
     "mfmg_assemble_coeffs": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(_BC), _VP,
                                             ctypes.POINTER(_VP)]),
@@ -189,10 +193,32 @@ class Octree:
                                       kind.ctypes.data_as(_VP)))
         return owner, d, other, kind
 
+    def leaves_device(self):
+        """leaves() as device tensors, written on the current stream."""
+        torch = _torch()
+        lev = torch.empty(max(1, self.n_leaves), dtype=torch.uint8, device="cuda")
+        ijk = torch.empty((max(1, self.n_leaves), 3), dtype=torch.int32, device="cuda")
+        _check(_lib.mfmg_octree_leaves_device(self._h, _ptr(lev), _ptr(ijk), _stream()))
+        return lev[:self.n_leaves], ijk[:self.n_leaves]
 
-def build_octree(spec):
-    """Host octree from a spec dict {min_level, max_level, node_size, prims}
-    (prims: dicts with kind, center, radius, band, lo, hi)."""
+    def faces_device(self):
+        """faces() as device tensors, written on the current stream."""
+        torch = _torch()
+        n = max(1, self.n_faces)
+        owner = torch.empty(n, dtype=torch.int64, device="cuda")
+        d = torch.empty(n, dtype=torch.int8, device="cuda")
+        other = torch.empty(n, dtype=torch.int64, device="cuda")
+        kind = torch.empty(n, dtype=torch.int8, device="cuda")
+        _check(_lib.mfmg_octree_faces_device(self._h, _ptr(owner), _ptr(d), _ptr(other),
+                                             _ptr(kind), _stream()))
+        k = self.n_faces
+        return owner[:k], d[:k], other[:k], kind[:k]
+
+
+def build_octree(spec, device=False):
+    """Octree from a spec dict {min_level, max_level, node_size, prims}
+    (prims: dicts with kind, center, radius, band, lo, hi), built on the
+    host, or with device=True on the device (current stream)."""
     lib = load_library()
     prims = spec.get("prims", [])
     arr = (_Prim * max(1, len(prims)))()
@@ -207,7 +233,10 @@ def build_octree(spec):
     s = _Spec(int(spec["min_level"]), int(spec["max_level"]),
               int(spec.get("node_size", 4)), len(prims), arr)
     h = _VP()
-    _check(lib.mfmg_build_octree(ctypes.byref(s), ctypes.byref(h)))
+    if device:
+        _check(lib.mfmg_build_octree_device(ctypes.byref(s), _stream(), ctypes.byref(h)))
+    else:
+        _check(lib.mfmg_build_octree(ctypes.byref(s), ctypes.byref(h)))
     return Octree(h)
 
 
