@@ -9,7 +9,8 @@ benchmark times (default hierarchy, rtol 1e-10, FP64 and mixed cycle):
 * leaf levels 7..10 (26.3M leaves): topology bit-exact against the oracle
   octree and faces, and the relative residual of both GPU solutions
   measured with the oracle's assembled operator (the oracle's own solve at
-  this size is left to the benchmark's bounded sample).
+  this size is left to the benchmark's bounded sample); the same octree
+  built on the device, bit-exact against the oracle too.
 """
 
 import numpy as np
@@ -130,3 +131,20 @@ def test_largest_workload_topology_and_residual():
         sols.append(p)
         del h
     assert rel(sols[1], sols[0]) <= 1e-8
+
+
+def test_largest_workload_built_on_the_device():
+    """26.3M leaves, octree built on the device: leaves and faces bit-exact
+    against the oracle octree."""
+    from paper_2604_18886_amd import mfmg
+    case = _case(4)
+    td = mfmg.build_octree(case.spec, device=True)
+    lev, ijk = td.leaves()
+    assert np.array_equal(lev, case.T.level)
+    assert np.array_equal(ijk, case.T.ijk)
+    del lev, ijk
+    owner, d, other, kind = td.faces()
+    assert np.array_equal(owner, case.disc.face_owner)
+    assert np.array_equal(d, case.disc.face_dir)
+    assert np.array_equal(other, case.disc.face_other)
+    assert np.array_equal(kind, case.disc.face_kind)
