@@ -77,24 +77,31 @@ def summarize_pmc(fetch_csv, write_csv, level):
     COPY_BYTES bytes."""
     import csv
 
-    def per_kernel(path, counter):
-        rows = {}
+    def dispatches(path, counter):
+        """(dispatch id, kernel name, bytes) in dispatch order; a counter
+        summed over its instances."""
+        acc = {}
         with open(path) as fh:
             for r in csv.DictReader(fh):
                 if r.get("Counter_Name") != counter:
                     continue
-                rows.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
-        return rows
+                key = int(r["Dispatch_Id"])
+                name, v = acc.get(key, (r["Kernel_Name"], 0.0))
+                acc[key] = (name, v + float(r["Counter_Value"]) * 1024.0)
+        return [(k, n, v) for k, (n, v) in sorted(acc.items())]
 
     out = {}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
-        rows = per_kernel(path, counter)
-        smooth = [v for k, v in rows.items() if "k_smooth" in k]
-        copy = [v for k, v in rows.items() if "copy" in k.lower() or "elementwise" in k]
-        if not smooth or not copy:
-            raise SystemExit(f"{path}: no k_smooth or copy dispatches for {counter}")
-        smooth = smooth[0]
-        copy = max(copy, key=lambda v: sum(v) / len(v))
+        rows = dispatches(path, counter)
+        smooth = [v for _, n, v in rows if "k_smooth" in n]
+        last = max((d for d, n, _ in rows if "k_smooth" in n), default=None)
+        # the TRAFFIC_REPS device copies of COPY_BYTES that follow the
+        # half-sweeps (earlier copy dispatches move other, smaller buffers)
+        copy = [v for d, n, v in rows
+                if last is not None and d > last and "copy" in n.lower()]
+        if not smooth or len(copy) != TRAFFIC_REPS:
+            raise SystemExit(f"{path}: expected k_smooth dispatches followed by "
+                             f"{TRAFFIC_REPS} copies for {counter}")
         factor = (sum(copy) / len(copy)) / COPY_BYTES
         out[counter] = {"per_launch_bytes_raw": sum(smooth) / len(smooth),
                         "launches": len(smooth), "copy_raw_bytes": sum(copy) / len(copy),
