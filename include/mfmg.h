@@ -49,7 +49,8 @@ typedef enum {
   MFMG_ERR_HIP = -3,             /* a HIP runtime call failed                */
   MFMG_ERR_OOM = -4,             /* device or host allocation failed         */
   MFMG_ERR_BREAKDOWN = -5,       /* (p,Ap) <= 0, (r,z) <= 0 or non-finite    */
-  MFMG_ERR_INCOMPATIBLE_RHS = -6 /* reserved: all-Neumann with 1^T rhs != 0  */
+  MFMG_ERR_INCOMPATIBLE_RHS = -6 /* no Dirichlet face, null-space shift off */
+                                 /* and 1^T rhs != 0 over the active cells  */
 } mfmg_status;
 
 typedef struct mfmg_octree mfmg_octree;
@@ -239,7 +240,10 @@ typedef struct {
  * in canonical order; entries of inactive leaves are ignored on input and
  * set to 0 on output.  hist (host, may be NULL) receives max_iter + 1
  * relative residuals (the first iters + 1 are meaningful).
- * Returns OK, NOT_CONVERGED (p holds the last iterate), BREAKDOWN, or an
+ * Returns OK, NOT_CONVERGED (p holds the last iterate), BREAKDOWN,
+ * INCOMPATIBLE_RHS (null_space = 0 on a problem without Dirichlet faces and
+ * |sum of rhs| > 1e-10 sum of |rhs| over the active cells: A is singular on
+ * the constants and the system has no solution; nothing is solved), or an
  * error. */
 mfmg_status mfmg_pcg_solve(mfmg_hierarchy *h, const double *rhs, double *p,
                            const mfmg_solve_params *params, void *stream,
@@ -249,7 +253,8 @@ mfmg_status mfmg_pcg_solve(mfmg_hierarchy *h, const double *rhs, double *p,
  * the exact transpose of the cycle, then per face
  *   dL/dbeta_f = -lambda^T (dA/dbeta_f) p
  * (0 at Neumann walls and where a side of the face is inactive).
- * p, dL_dp, lambda: device, n_leaves; dL_dbeta: device, n_faces. */
+ * p, dL_dp, lambda: device, n_leaves; dL_dbeta: device, n_faces.
+ * INCOMPATIBLE_RHS as for mfmg_pcg_solve, with dL_dp in place of rhs. */
 mfmg_status mfmg_pcg_solve_adjoint(mfmg_hierarchy *h, const double *p,
                                    const double *dL_dp, double *lambda,
                                    double *dL_dbeta,

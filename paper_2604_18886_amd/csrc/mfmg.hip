@@ -1341,12 +1341,33 @@ struct Reduce {
     hipLaunchKernelGGL(k_shift_mean<V>, dim3(G), dim3(kBlock), 0, s, P, v, v_low, na, mode);
     if (mode != 3) finish(G, kFinShift, mode, rtol);
   }
+  // sum over the active cells of v (canonical order) or of |v|, on the host
+  double active_sum(const double *v, int absval, const double *dev_sum) const {
+    hipLaunchKernelGGL(k_sum_active_canon, dim3(G), dim3(kBlock), 0, s, P, v, absval);
+    finish(G, kFinSum);
+    double x = 0.0;
+    HIP_CHECK(hipMemcpyAsync(&x, dev_sum, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    return x;
+  }
   void true_resid(const double *rhs, const double *X, uint32_t nlb) const {
     unsigned g = level_grid(nlb);
     hipLaunchKernelGGL(k_true_resid, dim3(g), dim3(kBlock), 0, s, P, rhs, X);
     finish(g, kFinTrue);
   }
 };
+
+// Without a Dirichlet face A is singular on the constants of the active
+// cells (Section 2.2); with the null-space shift off, a right-hand side whose
+// active sum is not zero (relative to the sum of its magnitudes) has no
+// solution.
+static bool incompatible_rhs(mfmg_hierarchy *h, const double *rhs, hipStream_t s) {
+  Reduce R(h, s);
+  const double *dev_sum = &h->S.p->sum;
+  double sum = R.active_sum(rhs, 0, dev_sum);
+  double mag = R.active_sum(rhs, 1, dev_sum);
+  return std::fabs(sum) > 1e-10 * mag;
+}
 
 // Launch helpers of one Krylov iteration (Algorithm 1).
 template <class V>
@@ -1526,6 +1547,10 @@ extern "C" mfmg_status mfmg_pcg_solve(mfmg_hierarchy *h, const double *rhs, doub
       h->drop_graphs();  // they hold the old history pointer
       h->hist.alloc(std::max<size_t>(size_t(sp->max_iter) + 2, 1024));
     }
+    if (!ns && !h->co->has_dirichlet && incompatible_rhs(h, rhs, s))
+      return fail(MFMG_ERR_INCOMPATIBLE_RHS,
+                  "no Dirichlet face and the null-space shift is off, but the right-hand "
+                  "side does not sum to zero over the active cells");
     hipEvent_t e0, e1;
     HIP_CHECK(hipEventCreate(&e0));
     HIP_CHECK(hipEventCreate(&e1));
@@ -1631,6 +1656,10 @@ extern "C" mfmg_status mfmg_pcg_solve_adjoint(mfmg_hierarchy *h, const double *p
       h->drop_graphs();  // they hold the old history pointer
       h->hist.alloc(std::max<size_t>(size_t(sp->max_iter) + 2, 1024));
     }
+    if (!ns && !h->co->has_dirichlet && incompatible_rhs(h, dL_dp, s))
+      return fail(MFMG_ERR_INCOMPATIBLE_RHS,
+                  "no Dirichlet face and the null-space shift is off, but dL/dp does not "
+                  "sum to zero over the active cells");
     if (!h->rA.p) h->rA.alloc(size_t(D.nlb) * 64);
     if (!h->f_owner.p) {
       // canonical face list and per-brick tables for the gradient

@@ -512,6 +512,20 @@ __global__ void __launch_bounds__(kBlock) k_sum_active(PcgArgs P, const double *
   block_partial(part, P.partials);
 }
 
+// sum of v (canonical order) over the active cells, or of |v| (absval)
+__global__ void __launch_bounds__(kBlock) k_sum_active_canon(PcgArgs P, const double *v,
+                                                             int absval) {
+  double part = 0.0;
+  LEAF_LOOP(P) {
+    const BrickMeta M = P.T.meta[b];
+    if ((act_mask(M) >> m) & 1ull) {
+      double x = v[int64_t(P.canon[b]) * 64 + m];
+      part += absval ? fabs(x) : x;
+    }
+  }
+  block_partial(part, P.partials);
+}
+
 // v -= sum / n_active on active cells and ||v||^2; mode 0: initial residual
 // (sets rr0, tolerance, done), 1: iteration residual (stop test), 2: true
 // residual (tr), 3: solution (no norm)

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libmfmg.so")
 
 OK = 0
 NOT_CONVERGED = 1
+INCOMPATIBLE_RHS = -6
 SPHERE, BOX = 0, 1
 NEUMANN, DIRICHLET = 0, 1
 FP64, MIXED = 0, 1

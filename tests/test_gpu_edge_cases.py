@@ -2,7 +2,8 @@
 level is its coarsest (the cycle is the coarsest smoother alone), cycle
 parameters other than the defaults (smoothing counts, coarsest level, the
 coarse-correction factor), a zero right-hand side, a domain that is almost
-all solid, and a solve stopped by its iteration limit."""
+all solid, a solve stopped by its iteration limit, and a right-hand side
+incompatible with a singular operator."""
 
 import numpy as np
 import pytest
@@ -148,3 +149,25 @@ def test_iteration_limit():
                      active=case.disc.active)
     assert info["iters"] == 3
     assert rel(p.cpu().numpy(), x3) <= 1e-10
+
+
+def test_incompatible_right_hand_side():
+    """No Dirichlet face and the null-space shift off: a right-hand side
+    (or dL/dp) that does not sum to zero over the active cells has no
+    solution and is rejected before any iteration; a zero-sum one is
+    accepted."""
+    from paper_2604_18886_amd import mfmg
+    case = Case(3, problems.config_spec(3, 4, 6), bc=(0,) * 6, theta=0.5)
+    act = case.disc.active
+    h = _hierarchy(case, coarsest_level=3)
+    rhs = _seeded_rhs(case, 64)
+    rhs[act] -= rhs[act].mean()
+    bad = np.where(act, rhs + 1e-3, 0.0)
+    with pytest.raises(mfmg.MFMGError) as e:
+        mfmg.pcg_solve(h, case.device(bad), rtol=1e-10, null_space=0)
+    assert e.value.status == mfmg.INCOMPATIBLE_RHS
+    p, st = mfmg.pcg_solve(h, case.device(rhs), rtol=1e-10)  # automatic shift
+    assert st["status"] == 0
+    with pytest.raises(mfmg.MFMGError) as e:
+        mfmg.pcg_solve_adjoint(h, p, case.device(bad), rtol=1e-10, null_space=0)
+    assert e.value.status == mfmg.INCOMPATIBLE_RHS
