@@ -146,6 +146,47 @@ def cpu_baseline(sample_levels=(6, 9)):
                        f"NumPy/SciPy FP64, 1 thread of {os.cpu_count()}")}
 
 
+def projection_timing(mfmg, torch, h, beta_d, fdir, kind, bc, reps=5):
+    """The projection wrapper on the workload with the static test's field
+    u = (0, -1, 0) (zero on solid walls): wall time of the divergence and
+    of the velocity update (best of reps), one projection end to end, and
+    the volume-weighted RMS divergence before and after."""
+    import numpy as np
+    d = np.asarray(fdir)
+    u = np.where((d >> 1) == 1, -1.0, 0.0)
+    u[(np.asarray(kind) == 0) & (np.asarray(bc)[d] == 0)] = 0.0
+    u0 = torch.as_tensor(u, dtype=torch.float64, device="cuda")
+    del u
+    uw = u0.clone()
+
+    def best(fn):
+        fn()
+        t = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            t.append(time.perf_counter() - t0)
+        return min(t) * 1e3
+
+    div = mfmg.divergence(h, beta_d, u0)
+    pz = torch.zeros_like(div)
+    ms_div = best(lambda: mfmg.divergence(h, beta_d, u0))
+    ms_upd = best(lambda: mfmg.project_velocity(h, beta_d, pz, uw))
+    uw.copy_(u0)
+    mfmg.project(h, beta_d, uw)
+    uw.copy_(u0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st, rms0, rms1 = mfmg.project(h, beta_d, uw)
+    torch.cuda.synchronize()
+    total = (time.perf_counter() - t0) * 1e3
+    return {"divergence_ms": ms_div, "update_ms": ms_upd, "projection_ms": total,
+            "iters": st["iters"], "rms_div_before": rms0, "rms_div_after": rms1,
+            "field": "u = (0, -1, 0), zero on solid walls", "rtol": 1e-10}
+
+
 def rebuild_timing(mfmg, torch, spec, beta_d, bc, theta, reps=3):
     """Wall time of the steps that rebuild the solver for a changed octree
     on the device (octree, canonical face list, assembly, Algorithm 3
@@ -306,6 +347,11 @@ def main():
     del hw
     log(f"[bench] mixed W-cycle (mu=2): {dt_w * 1e3:.2f} ms/solve, {stw['iters']} iterations, "
         f"true residual {stw['rel_resid_true']:.2e}")
+    proj = projection_timing(mfmg, torch, hiers["mixed"], beta_d, fdir, kind, bc)
+    log(f"[bench] projection (mixed): divergence {proj['divergence_ms']:.2f} ms, velocity "
+        f"update {proj['update_ms']:.2f} ms, whole projection {proj['projection_ms']:.1f} ms "
+        f"({proj['iters']} iterations); RMS_V of the divergence {proj['rms_div_before']:.3e} -> "
+        f"{proj['rms_div_after']:.3e}")
     rebuild = rebuild_timing(mfmg, torch, spec, beta_d, bc, theta)
     log(f"[bench] rebuild on the device: octree {rebuild['octree_ms']:.1f} ms (host build "
         f"{rebuild['host_octree_ms']:.0f} ms), face list {rebuild['faces_ms']:.1f} ms, "
@@ -358,6 +404,7 @@ def main():
                   "adjoint_ms": head["adjoint_ms"], "adjoint_iters": head["adjoint_iters"],
                   "wcycle_ms_per_solve": dt_w * 1e3, "wcycle_iters": stw["iters"]},
         "rebuild": rebuild,
+        "projection": proj,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

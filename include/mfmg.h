@@ -261,6 +261,37 @@ mfmg_status mfmg_pcg_solve_adjoint(mfmg_hierarchy *h, const double *p,
                                    const mfmg_solve_params *params,
                                    void *stream, mfmg_solve_stats *stats);
 
+/* --------------------------------------------------------------- projection
+ * The steps around a solve that project a face velocity field (Section
+ * 2.1: the pressure equation's flux form; Section 4.4: the static
+ * projection test; RMS_V of Section 4.2).  Velocities are MAC normal
+ * components on the canonical faces, along the + axis of the face's axis;
+ * a face's fluid area is beta_f h^2 (h of its owner, the finer side), with
+ * the same beta as the assembly.  Device vectors; kernels are queued on
+ * stream. */
+
+/* div (n_leaves, canonical): the integrated divergence of face_u (the net
+ * outflow sum_f s beta_f h^2 u_f of each leaf, s = +1 where the + axis
+ * points out of it): the right-hand side that makes A p = div the
+ * projection's pressure equation. */
+mfmg_status mfmg_divergence(mfmg_hierarchy *h, const double *face_beta,
+                            const double *face_u, double *div, void *stream);
+
+/* face_u -= s_o F_f / (beta_f h^2) on every face with beta_f > 0, F_f the
+ * pressure flux of the operator through the face (same level:
+ * k (p_o - p_t); T-junction: k (mean of p over the fine owner's active
+ * siblings - p_t) / 2; Dirichlet wall: k p_o; Neumann wall or an inactive
+ * side: 0), so that div(u_new) = div(u) - A p: after a solve of A p = div(u)
+ * the divergence left is the solve's residual.  The first call makes the
+ * hierarchy's canonical face list (n_faces x 18 bytes), which it keeps. */
+mfmg_status mfmg_project_velocity(mfmg_hierarchy *h, const double *face_beta,
+                                  const double *p, double *face_u, void *stream);
+
+/* *rms (host) = sqrt(sum V_i (div_i / V_i)^2 / sum V_i) over the active
+ * leaves, V_i = h_i^3.  Returns after the stream has drained. */
+mfmg_status mfmg_divergence_rms(mfmg_hierarchy *h, const double *div, double *rms,
+                                void *stream);
+
 /* ------------------------------------------------ component entry points
  * For parity tests of single steps.  Device vectors of n_leaves doubles. */
 

@@ -15,6 +15,7 @@
 #include "kernels.hpp"
 #include "octree_kernels.hpp"
 #include "pcg_kernels.hpp"
+#include "projection_kernels.hpp"
 #include "topology.hpp"
 
 using namespace mfmg;
@@ -1357,6 +1358,34 @@ struct Reduce {
   }
 };
 
+// The canonical face list with the per-brick levels and activity masks in
+// canonical order (for per-face kernels), made at first use and kept.
+static void ensure_face_list(mfmg_hierarchy *h, hipStream_t s) {
+  if (h->f_owner.p) return;
+  const DeviceTopology &D = *h->co->dt;
+  size_t nf = size_t(std::max<int64_t>(h->co->tree->n_faces, 1));
+  h->f_owner.alloc(nf);
+  h->f_other.alloc(nf);
+  h->f_dir.alloc(nf);
+  h->f_kind.alloc(nf);
+  h->leaf_level.alloc(size_t(D.nlb));
+  h->canon_act.alloc(size_t(D.nlb));
+  if (D.nlb) {
+    hipLaunchKernelGGL(k_oct_faces, dim3(grid_for(D.nlb)), dim3(kBlock), 0, s,
+                       (const BrickMeta *)D.meta.p, (const int32_t *)D.canon.p,
+                       (const int64_t *)D.fbase.p, (const uint8_t *)D.fmask.p, D.nlb,
+                       h->f_owner.p, h->f_dir.p, h->f_other.p, h->f_kind.p);
+    hipLaunchKernelGGL(k_oct_canon_level, dim3(grid_elems(D.nlb, 256)), dim3(256), 0, s,
+                       (const BrickMeta *)D.meta.p, (const int32_t *)D.canon.p, D.nlb,
+                       h->leaf_level.p);
+    hipLaunchKernelGGL(k_canonical_act, dim3(grid_elems(D.nlb, 256)), dim3(256), 0, s,
+                       (const BrickMeta *)h->meta.p, (const int32_t *)D.canon.p, D.nlb,
+                       h->canon_act.p);
+  }
+  HIP_CHECK(hipGetLastError());
+  HIP_CHECK(hipStreamSynchronize(s));
+}
+
 // Without a Dirichlet face A is singular on the constants of the active
 // cells (Section 2.2); with the null-space shift off, a right-hand side whose
 // active sum is not zero (relative to the sum of its magnitudes) has no
@@ -1661,29 +1690,7 @@ extern "C" mfmg_status mfmg_pcg_solve_adjoint(mfmg_hierarchy *h, const double *p
                   "no Dirichlet face and the null-space shift is off, but dL/dp does not "
                   "sum to zero over the active cells");
     if (!h->rA.p) h->rA.alloc(size_t(D.nlb) * 64);
-    if (!h->f_owner.p) {
-      // canonical face list and per-brick tables for the gradient
-      size_t nf = size_t(std::max<int64_t>(T.n_faces, 1));
-      h->f_owner.alloc(nf);
-      h->f_other.alloc(nf);
-      h->f_dir.alloc(nf);
-      h->f_kind.alloc(nf);
-      h->leaf_level.alloc(size_t(D.nlb));
-      if (D.nlb) {
-        hipLaunchKernelGGL(k_oct_faces, dim3(grid_for(D.nlb)), dim3(kBlock), 0, s,
-                           (const BrickMeta *)D.meta.p, (const int32_t *)D.canon.p,
-                           (const int64_t *)D.fbase.p, (const uint8_t *)D.fmask.p, D.nlb,
-                           h->f_owner.p, h->f_dir.p, h->f_other.p, h->f_kind.p);
-        hipLaunchKernelGGL(k_oct_canon_level, dim3(grid_elems(D.nlb, 256)), dim3(256), 0, s,
-                           (const BrickMeta *)D.meta.p, (const int32_t *)D.canon.p, D.nlb,
-                           h->leaf_level.p);
-      }
-      h->canon_act.alloc(size_t(D.nlb));
-      hipLaunchKernelGGL(k_canonical_act, dim3(grid_elems(D.nlb, 256)), dim3(256), 0, s,
-                         (const BrickMeta *)h->meta.p, (const int32_t *)D.canon.p, D.nlb,
-                         h->canon_act.p);
-      HIP_CHECK(hipStreamSynchronize(s));
-    }
+    ensure_face_list(h, s);
     hipEvent_t e0, e1;
     HIP_CHECK(hipEventCreate(&e0));
     HIP_CHECK(hipEventCreate(&e1));
@@ -1858,6 +1865,83 @@ extern "C" mfmg_status mfmg_profile(mfmg_hierarchy *h, int what, int level, int 
                                                        : 2.0 * double(kCopyBytes);
   } catch (const HipError &e) {
     return fail(MFMG_ERR_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  }
+  return MFMG_OK;
+}
+
+// --------------------------------------------------------------------------
+// projection of a face velocity field
+// --------------------------------------------------------------------------
+extern "C" mfmg_status mfmg_divergence(mfmg_hierarchy *h, const double *face_beta,
+                                       const double *face_u, double *div, void *stream) {
+  if (!h || !face_beta || !face_u || !div) return fail(MFMG_ERR_INVALID_ARG, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  try {
+    const DeviceTopology &D = *h->co->dt;
+    DivArgs A;
+    A.T = make_topo(D, h->meta.p);
+    A.fbase = D.fbase.p;
+    A.fmask = D.fmask.p;
+    A.canon = D.canon.p;
+    A.beta = face_beta;
+    A.u = face_u;
+    A.div = div;
+    if (D.nlb) hipLaunchKernelGGL(k_divergence, dim3(grid_for(D.nlb)), dim3(kBlock), 0, s, A);
+    HIP_CHECK(hipGetLastError());
+  } catch (const HipError &e) {
+    return hip_fail(e);
+  }
+  return MFMG_OK;
+}
+
+extern "C" mfmg_status mfmg_project_velocity(mfmg_hierarchy *h, const double *face_beta,
+                                             const double *p, double *face_u, void *stream) {
+  if (!h || !face_beta || !p || !face_u) return fail(MFMG_ERR_INVALID_ARG, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  try {
+    ensure_face_list(h, s);
+    FluxArgs A;
+    A.owner = h->f_owner.p;
+    A.other = h->f_other.p;
+    A.dir = h->f_dir.p;
+    A.kind = h->f_kind.p;
+    A.level = h->leaf_level.p;
+    A.act = h->canon_act.p;
+    A.beta = face_beta;
+    A.p = p;
+    for (int d = 0; d < 6; ++d) A.bc[d] = h->co->bc.bc[d];
+    A.theta = h->co->bc.theta;
+    A.n_faces = h->co->tree->n_faces;
+    A.u = face_u;
+    if (A.n_faces)
+      hipLaunchKernelGGL(k_project_velocity, dim3(grid_elems(A.n_faces, 256)), dim3(256), 0, s,
+                         A);
+    HIP_CHECK(hipGetLastError());
+  } catch (const HipError &e) {
+    return hip_fail(e);
+  } catch (const std::bad_alloc &) {
+    return fail(MFMG_ERR_OOM, "host allocation failed");
+  }
+  return MFMG_OK;
+}
+
+extern "C" mfmg_status mfmg_divergence_rms(mfmg_hierarchy *h, const double *div, double *rms,
+                                           void *stream) {
+  if (!h || !div || !rms) return fail(MFMG_ERR_INVALID_ARG, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  try {
+    Reduce R(h, s);
+    const double *dev_sum = &h->S.p->sum;
+    double part[2];
+    for (int what = 0; what < 2; ++what) {
+      hipLaunchKernelGGL(k_div_rms_part, dim3(R.G), dim3(kBlock), 0, s, R.P, div, what);
+      R.finish(R.G, kFinSum);
+      HIP_CHECK(hipMemcpyAsync(&part[what], dev_sum, sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    HIP_CHECK(hipStreamSynchronize(s));
+    *rms = part[1] > 0.0 ? std::sqrt(part[0] / part[1]) : 0.0;
+  } catch (const HipError &e) {
+    return hip_fail(e);
   }
   return MFMG_OK;
 }

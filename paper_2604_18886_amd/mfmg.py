@@ -99,6 +99,9 @@ SIGNATURES = {
     "mfmg_pcg_solve_adjoint": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP,
                                               ctypes.POINTER(_SolveParams), _VP,
                                               ctypes.POINTER(SolveStats)]),
+    "mfmg_divergence": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "mfmg_project_velocity": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "mfmg_divergence_rms": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(ctypes.c_double), _VP]),
     "mfmg_apply_operator": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int, _VP]),
     "mfmg_apply_precond": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int, _VP]),
     "mfmg_profile": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP,
@@ -355,6 +358,41 @@ def pcg_solve_adjoint(h, p, dL_dp, rtol=1e-10, max_iter=200, null_space=-1):
                                          ctypes.byref(sp), _stream(), ctypes.byref(st))
     _check(status, allow_not_converged=True)
     return lam, g, st.as_dict()
+
+
+# ------------------------------------------------------------------ projection
+def divergence(h, beta, u):
+    """Integrated divergence (canonical leaf order) of face velocities u
+    with face fluid fractions beta (device tensors, canonical face order)."""
+    torch = _torch()
+    div = torch.empty(h.n_leaves, dtype=torch.float64, device="cuda")
+    _check(_lib.mfmg_divergence(h._h, _ptr(beta), _ptr(u), _ptr(div), _stream()))
+    return div
+
+
+def project_velocity(h, beta, p, u):
+    """u -= s F(p) / (beta h^2) in place (see mfmg_project_velocity)."""
+    _check(_lib.mfmg_project_velocity(h._h, _ptr(beta), _ptr(p), _ptr(u), _stream()))
+    return u
+
+
+def divergence_rms(h, div):
+    """Volume-weighted RMS of div_i / V_i over the active leaves."""
+    r = ctypes.c_double()
+    _check(_lib.mfmg_divergence_rms(h._h, _ptr(div), ctypes.byref(r), _stream()))
+    return r.value
+
+
+def project(h, beta, u, rtol=1e-10, max_iter=200):
+    """One pressure projection of the face velocities u (in place):
+    rhs = div(u), solve A p = rhs, update u.  Returns (p, solve stats,
+    RMS of the divergence before, after)."""
+    div = divergence(h, beta, u)
+    rms0 = divergence_rms(h, div)
+    p, st = pcg_solve(h, div, rtol=rtol, max_iter=max_iter)
+    project_velocity(h, beta, p, u)
+    rms1 = divergence_rms(h, divergence(h, beta, u))
+    return p, st, rms0, rms1
 
 
 def apply_operator(h, x, transpose=False):
