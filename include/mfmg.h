@@ -195,7 +195,12 @@ typedef struct {
   int precision;      /* MFMG_FP64 or MFMG_MIXED                             */
 } mfmg_mg_params;
 
-/* Build the hierarchy for coeffs (which must outlive it). */
+/* Build the hierarchy for coeffs (which must outlive it).  The stencil
+ * kernels use 32-bit buffer offsets: INVALID_ARG (nothing allocated) when
+ * the FP64 leaf coefficients (read by the outer operator in both
+ * precisions), the level coefficients of the chosen precision or the
+ * plus-face table exceed 4 GiB, or an FP64 level vector reaches 2 GiB
+ * (from 2^21 leaf bricks on; in FP64 from about 2^21 bricks in all). */
 mfmg_status mfmg_build_hierarchy(const mfmg_coeffs *coeffs,
                                  const mfmg_mg_params *params, void *stream,
                                  mfmg_hierarchy **out);

@@ -799,15 +799,20 @@ extern "C" mfmg_status mfmg_build_hierarchy(const mfmg_coeffs *co, const mfmg_mg
   int64_t nlc = (int64_t(1) << prm->coarsest_level) / kBrick;
   if (nlc * nlc * nlc > 64) return fail(MFMG_ERR_INVALID_ARG, "coarsest level too large");
   {
-    // the level kernels address their arrays with 32-bit byte offsets
+    // The stencil kernels address their arrays with 32-bit byte offsets:
+    // coefficient and plus-face arrays must stay within 4 GiB, the vectors
+    // they read across faces below 2 GiB (an offset with bit 31 set is the
+    // out-of-range load of a wall or T-face).  The FP64 composite operator
+    // of the outer iteration runs in both precisions.
     const DeviceTopology &D = *co->dt;
-    uint64_t nb = D.nb, nlb = D.nlb, big;
+    uint64_t nb = D.nb, nlb = D.nlb;
+    uint64_t big = std::max(nlb * 256 * sizeof(double), nb * 48 * sizeof(double));
+    uint64_t vec = nb * 64 * sizeof(double);
     if (prm->precision == MFMG_FP64)
-      big = nb * 256 * sizeof(double);
+      big = std::max(big, nb * 256 * sizeof(double));
     else
-      big = std::max(nlb * 256 * sizeof(float), (nb - nlb) * 256 * sizeof(__half));
-    uint64_t ubytes = nb * 64 * (prm->precision == MFMG_FP64 ? sizeof(double) : sizeof(float));
-    if (big > kMaxBufferBytes || ubytes >= kOutOfRange)
+      big = std::max({big, nlb * 256 * sizeof(float), (nb - nlb) * 256 * sizeof(__half)});
+    if (big > kMaxBufferBytes || vec >= kOutOfRange)
       return fail(MFMG_ERR_INVALID_ARG, "level arrays exceed the 32-bit offset range");
   }
   hipStream_t s = (hipStream_t)stream;

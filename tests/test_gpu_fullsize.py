@@ -148,3 +148,45 @@ def test_largest_workload_built_on_the_device():
     assert np.array_equal(d, case.disc.face_dir)
     assert np.array_equal(other, case.disc.face_other)
     assert np.array_equal(kind, case.disc.face_kind)
+
+
+def test_offset_limit_and_largest_mixed_solve():
+    """Maximum sizes of the 32-bit buffer offsets.  Uniform 512^3 (2^21 leaf
+    bricks): the FP64 leaf coefficients the outer operator reads take
+    exactly 4 GiB, one byte too many, and both precisions are rejected
+    before any allocation.  A sphere band on levels 8..10 with 2.04M leaf
+    bricks (131M leaves, octree built on the device, beta = 1): FP64 is
+    rejected (its level coefficients of all bricks exceed 4 GiB), the mixed
+    hierarchy fits and solves a seeded right-hand side to rtol 1e-10 (true
+    residual recomputed in FP64 on the device)."""
+    import torch
+    from paper_2604_18886_amd import mfmg
+    bc = (0, 0, 0, 1, 0, 0)
+    tree = mfmg.build_octree(problems.uniform_spec(9), device=True)
+    assert tree.n_leaf_bricks == 2 ** 21
+    beta = torch.ones(tree.n_faces, dtype=torch.float64, device="cuda")
+    co = mfmg.assemble_coeffs(tree, beta, bc, 0.5)
+    for precision in (mfmg.FP64, mfmg.MIXED):
+        with pytest.raises(mfmg.MFMGError) as e:
+            mfmg.build_hierarchy(co, precision=precision)
+        assert e.value.status == -1 and "32-bit" in str(e.value)
+    del co, beta, tree
+    spec = {"min_level": 8, "max_level": 10, "node_size": 4,
+            "prims": [problems.sphere_prim((0.5, 0.5, 0.5), 0.3, 0.04)]}
+    tree = mfmg.build_octree(spec, device=True)
+    print(f"  {tree.n_leaves} leaves in {tree.n_leaf_bricks} leaf bricks, {tree.n_faces} faces",
+          flush=True)
+    assert 0.95 * 2 ** 21 < tree.n_leaf_bricks < 2 ** 21
+    beta = torch.ones(tree.n_faces, dtype=torch.float64, device="cuda")
+    co = mfmg.assemble_coeffs(tree, beta, bc, 0.5)
+    del beta
+    with pytest.raises(mfmg.MFMGError) as e:
+        mfmg.build_hierarchy(co, precision=mfmg.FP64)
+    assert e.value.status == -1
+    h = mfmg.build_hierarchy(co, precision=mfmg.MIXED)
+    g = torch.Generator(device="cuda").manual_seed(90)
+    rhs = torch.rand(tree.n_leaves, dtype=torch.float64, device="cuda", generator=g) - 0.5
+    p, st = mfmg.pcg_solve(h, rhs, rtol=1e-10)
+    print(f"  mixed: {st['iters']} iterations, true residual {st['rel_resid_true']:.2e}, "
+          f"{st['seconds'] * 1e3:.1f} ms", flush=True)
+    assert st["status"] == 0 and st["rel_resid_true"] <= 1.5e-10
