@@ -833,15 +833,17 @@ __global__ void __launch_bounds__(kBlock) k_T_apply(LevelArgsT<V, CL, CI> A, int
 }
 
 // Coupling of level l to the coarser leaves, transposed: on the leaf bricks
-// of level l-1 (the range), RHO_J += sum over the fine T-face cells f next
-// to J of (k_f / 2) W_f (the fine cells are children of J's inner neighbour).
+// of level l-1 that have an inner neighbour (list[0, n)), RHO_J += sum over
+// the fine T-face cells f next to J of (k_f / 2) W_f (the fine cells are
+// children of J's inner neighbour).
 template <class V, class CL, class CI>
-__global__ void __launch_bounds__(kBlock) k_T_coupling(LevelArgsT<V, CL, CI> A) {
+__global__ void __launch_bounds__(kBlock) k_T_coupling(LevelArgsT<V, CL, CI> A,
+                                                       const uint32_t *list, uint32_t n) {
   if (A.done && *A.done) return;
   uint32_t i = blockIdx.x * kWavesPerBlock + wave_id();
   int m = threadIdx.x & (kWave - 1);
-  if (i >= A.R.n()) return;
-  uint32_t b = A.R.brick(i);
+  if (i >= n) return;
+  uint32_t b = list[i];
   const BrickMeta M = A.T.meta[b];
   if (!(M.flags & kFlagInner)) return;
   if (!((act_mask(M) >> m) & 1ull)) return;
@@ -987,6 +989,19 @@ __global__ void __launch_bounds__(1024) k_T_coarsest(LevelArgsT<V, CL, CI> A, in
       __syncthreads();
     }
   }
+}
+
+// flag[b] = leaf brick b has an inner (finer-refined) face neighbour
+__global__ void k_couple_flag(const BrickMeta *meta, uint32_t nlb, int64_t *flag) {
+  uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nlb) flag[b] = (meta[b].flags & kFlagInner) ? 1 : 0;
+}
+
+// list[pos[b]] = b for the flagged bricks (pos: exclusive scan of the flags)
+__global__ void k_couple_list(const BrickMeta *meta, uint32_t nlb, const int64_t *pos,
+                              uint32_t *list) {
+  uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nlb && (meta[b].flags & kFlagInner)) list[pos[b]] = b;
 }
 
 template <class V>

@@ -199,6 +199,9 @@ struct mfmg_hierarchy {
   DevBuf<double> hist;
   // transposed cycle (allocated on first use): residual, solution, scratch
   DevBuf<double> T64[6];  // RHO, Y, W (nb*64), SBAR, YS ((nb-nlb)*64), W2 (nb*64)
+  // leaf bricks with an inner neighbour (level-major), per level [lo, lo + n)
+  DevBuf<uint32_t> couple;
+  std::vector<uint32_t> couple_lo, couple_n;
   DevBuf<float> T32[6];
   DevBuf<double> rA;              // adjoint PCG residual
   // face arrays for the per-face gradient (allocated on first use)
@@ -1140,9 +1143,10 @@ struct CycleT {
     if (l > h->lc) {
       auto C = args(l - 1, 1);
       C.W = win;
-      if (C.R.n())
-        hipLaunchKernelGGL((k_T_coupling<V, CL, CI>), dim3(grid_for(C.R.n())), dim3(kBlock), 0,
-                           s, C);
+      uint32_t n = h->couple_n[size_t(l - 1)];
+      if (n)
+        hipLaunchKernelGGL((k_T_coupling<V, CL, CI>), dim3(grid_for(n)), dim3(kBlock), 0, s, C,
+                           (const uint32_t *)h->couple.p + h->couple_lo[size_t(l - 1)], n);
     }
   }
   // Transpose of smooth(l, (c0, 1 - c0), nu): 2 nu half-sweeps with the
@@ -1218,10 +1222,43 @@ void alloc_transpose(const mfmg_hierarchy *hc, DevBuf<V> (&T)[6]) {
   T[5].alloc(size_t(nb) * 64);
 }
 
+// The leaf bricks whose coarse cells take the transposed T-junction coupling
+// (those with an inner face neighbour), per level, made at first use.
+static void ensure_coupling_lists(mfmg_hierarchy *h, hipStream_t s) {
+  if (!h->couple_n.empty()) return;
+  const DeviceTopology &D = *h->co->dt;
+  uint32_t nlb = D.nlb;
+  std::vector<int64_t> pos(size_t(nlb) + 1, 0);
+  DevBuf<int64_t> work, total;
+  work.alloc(std::max<size_t>(nlb, 1));
+  total.alloc(1);
+  hipLaunchKernelGGL(k_couple_flag, dim3(grid_elems(nlb, 256)), dim3(256), 0, s,
+                     (const BrickMeta *)D.meta.p, nlb, work.p);
+  scan_exclusive(work.p, int64_t(nlb), total.p, s);
+  HIP_CHECK(hipMemcpyAsync(pos.data(), work.p, size_t(nlb) * sizeof(int64_t),
+                           hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(pos.data() + nlb, total.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  h->couple.alloc(std::max<size_t>(size_t(pos[nlb]), 1));
+  hipLaunchKernelGGL(k_couple_list, dim3(grid_elems(nlb, 256)), dim3(256), 0, s,
+                     (const BrickMeta *)D.meta.p, nlb, (const int64_t *)work.p, h->couple.p);
+  HIP_CHECK(hipGetLastError());
+  h->couple_lo.assign(D.range.size(), 0);
+  h->couple_n.assign(D.range.size(), 0);
+  for (size_t l = 0; l < D.range.size(); ++l) {
+    const Range &R = D.range[l];
+    if (!R.n_leaf) continue;
+    h->couple_lo[l] = uint32_t(pos[R.leaf_lo]);
+    h->couple_n[l] = uint32_t(pos[R.leaf_lo + R.n_leaf] - pos[R.leaf_lo]);
+  }
+  HIP_CHECK(hipStreamSynchronize(s));  // work is freed on return
+}
+
 // z = M^T r: r, z FP64 leaf vectors in device order; returns the z buffer
 // (the Y leaf part, of the cycle's value type)
 void run_cycle_T(mfmg_hierarchy *h, const double *r, hipStream_t s,
                  const int *done = nullptr) {
+  ensure_coupling_lists(h, s);
   if (h->prm.precision == MFMG_MIXED) {
     alloc_transpose(h, h->T32);
     CycleT<float, float, __half> c{h, h->coef32.p, h->coef16.p, h->tc32.p, h->pf32.p,
