@@ -105,8 +105,8 @@ mfmg_status mfmg_build_octree(const mfmg_refine_spec *spec, mfmg_octree **out);
  * 4.4 GB of temporary device memory at max_level 12, 70 MB at 10), freed
  * before return.  Work is queued on stream; the call returns after the
  * stream has drained.  The octree holds device tables only: it serves
- * everything below except mfmg_hierarchy_level_bricks/_coeffs, and its
- * host leaves/faces are device outputs copied back (null stream).
+ * everything below, and its host leaves/faces are device outputs copied
+ * back (null stream).
  * Errors: INVALID_ARG (as mfmg_build_octree), OOM, HIP, TOPOLOGY (an
  * internal invariant failed). */
 mfmg_status mfmg_build_octree_device(const mfmg_refine_spec *spec, void *stream,

@@ -139,11 +139,8 @@ inline unsigned grid_reduce(int64_t bricks) {
 // objects
 // --------------------------------------------------------------------------
 // Device view of the topology.  Device brick ids are level-major (leaf bricks
-// by descending level then Morton order; inner bricks likewise); perm maps a
-// host brick id (canonical leaf order, then inner bricks) to its device id
-// (empty for an octree built on the device).
+// by descending level then Morton order; inner bricks likewise).
 struct DeviceTopology {
-  std::vector<int32_t> perm;          // host brick -> device brick
   DevBuf<BrickMeta> meta;             // act = 0
   DevBuf<int32_t> child;              // 8 per device brick
   DevBuf<int64_t> fbase;              // per device leaf cell
@@ -343,21 +340,23 @@ extern "C" void mfmg_destroy_octree(mfmg_octree *t) { delete t; }
 // --------------------------------------------------------------------------
 // device topology and coefficients
 // --------------------------------------------------------------------------
+// From the host topology: perm maps a host brick id (canonical leaf order,
+// then inner bricks) to its device id.
 static void build_device_topology(const Topology &T, DeviceTopology &D, hipStream_t s) {
   int64_t nlb = T.n_leaf_bricks, nb = T.n_bricks;
   D.nlb = uint32_t(nlb);
   D.nb = uint32_t(nb);
-  D.perm.assign(nb, -1);
+  std::vector<int32_t> perm(nb, -1);
   std::vector<int32_t> order(nlb);
   for (int64_t i = 0; i < nlb; ++i) order[i] = int32_t(i);
   std::stable_sort(order.begin(), order.end(),
                    [&](int32_t a, int32_t b) { return T.level[a] > T.level[b]; });
   std::vector<int32_t> canon(nlb);
   for (int64_t i = 0; i < nlb; ++i) {
-    D.perm[order[i]] = int32_t(i);
+    perm[order[i]] = int32_t(i);
     canon[i] = order[i];
   }
-  for (int64_t b = nlb; b < nb; ++b) D.perm[b] = int32_t(b);  // inner ids already level-major
+  for (int64_t b = nlb; b < nb; ++b) perm[b] = int32_t(b);  // inner ids already level-major
   int L = T.max_level;
   D.range.assign(L + 1, Range{0, 0, 0, 0});
   for (int64_t i = 0; i < nlb; ++i) {
@@ -373,37 +372,37 @@ static void build_device_topology(const Topology &T, DeviceTopology &D, hipStrea
   std::vector<BrickMeta> meta_host(nb, BrickMeta{});
   std::vector<int32_t> child(8 * nb, -1);
   for (int64_t b = 0; b < nb; ++b) {
-    BrickMeta &M = meta_host[D.perm[b]];
+    BrickMeta &M = meta_host[perm[b]];
     std::memset(&M, 0, sizeof(M));
     M.flags = 0;
     for (int d = 0; d < 6; ++d) {
       int32_t n = T.nbr[6 * b + d];
       if (n <= kCoarseBase) {
-        M.nbr[d] = encode_coarse(D.perm[decode_coarse(n)]);
+        M.nbr[d] = encode_coarse(perm[decode_coarse(n)]);
         M.flags |= 1u << d;
       } else if (n == kWall) {
         M.nbr[d] = kWall;
         M.flags |= 1u << (16 + d);
       } else {
-        M.nbr[d] = D.perm[n];
+        M.nbr[d] = perm[n];
         if (n >= nlb) M.flags |= 1u << (8 + d);
       }
     }
-    M.parent = T.parent[b] >= 0 ? D.perm[T.parent[b]] : -1;
+    M.parent = T.parent[b] >= 0 ? perm[T.parent[b]] : -1;
     M.tplus = b < nlb ? T.tplus[b] : -1;
     for (int a = 0; a < 3; ++a) M.coord[a] = T.coord[3 * b + a];
     M.level = T.level[b];
     for (int o = 0; o < 8; ++o) {
       int32_t c = T.child[8 * b + o];
-      child[8 * int64_t(D.perm[b]) + o] = c >= 0 ? D.perm[c] : -1;
+      child[8 * int64_t(perm[b]) + o] = c >= 0 ? perm[c] : -1;
     }
   }
   std::vector<int64_t> fbase(nlb * kCells);
   std::vector<uint8_t> fmask(nlb * kCells);
   for (int64_t b = 0; b < nlb; ++b)
     for (int m = 0; m < kCells; ++m) {
-      fbase[int64_t(D.perm[b]) * kCells + m] = T.cell_fbase[b * kCells + m];
-      fmask[int64_t(D.perm[b]) * kCells + m] = T.cell_fmask[b * kCells + m];
+      fbase[int64_t(perm[b]) * kCells + m] = T.cell_fbase[b * kCells + m];
+      fmask[int64_t(perm[b]) * kCells + m] = T.cell_fmask[b * kCells + m];
     }
   D.meta.upload(meta_host, s);
   D.child.upload(child, s);
@@ -919,21 +918,63 @@ extern "C" mfmg_status mfmg_build_hierarchy(const mfmg_coeffs *co, const mfmg_mg
   return MFMG_OK;
 }
 
+// Device ids of the bricks of a level in Morton order at that level (leaf
+// and inner bricks merged by their coordinates), with their records.
+static void level_order(const mfmg_hierarchy *h, int level, std::vector<int32_t> &ids,
+                        std::vector<BrickMeta> &recs, hipStream_t s) {
+  const DeviceTopology &D = *h->co->dt;
+  const Range &R = D.range[size_t(level)];
+  std::vector<BrickMeta> leaf(R.n_leaf), inner(R.n_inner);
+  if (R.n_leaf)
+    HIP_CHECK(hipMemcpyAsync(leaf.data(), D.meta.p + R.leaf_lo, R.n_leaf * sizeof(BrickMeta),
+                             hipMemcpyDeviceToHost, s));
+  if (R.n_inner)
+    HIP_CHECK(hipMemcpyAsync(inner.data(), D.meta.p + R.inner_lo,
+                             R.n_inner * sizeof(BrickMeta), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  auto key = [](const BrickMeta &M) {
+    uint64_t k = 0;
+    for (int i = 0; i < 21; ++i)
+      for (int a = 0; a < 3; ++a) k |= uint64_t((M.coord[a] >> i) & 1) << (3 * i + a);
+    return k;
+  };
+  // both ranges are in Morton order already: merge them
+  ids.clear();
+  recs.clear();
+  size_t i = 0, j = 0;
+  while (i < leaf.size() || j < inner.size()) {
+    bool take_leaf = j == inner.size() || (i < leaf.size() && key(leaf[i]) < key(inner[j]));
+    if (take_leaf) {
+      ids.push_back(int32_t(R.leaf_lo + i));
+      recs.push_back(leaf[i++]);
+    } else {
+      ids.push_back(int32_t(R.inner_lo + j));
+      recs.push_back(inner[j++]);
+    }
+  }
+}
+
 extern "C" mfmg_status mfmg_hierarchy_level_bricks(const mfmg_hierarchy *h, int level,
                                                    int64_t *count, int32_t *coords,
                                                    uint8_t *is_leaf) {
   if (!h || !count) return fail(MFMG_ERR_INVALID_ARG, "NULL argument");
-  if (!h->co->tree->on_host)
-    return fail(MFMG_ERR_INVALID_ARG, "needs an octree built on the host");
-  const Topology &T = h->co->tree->topo;
-  if (level < kMinLevel || level > T.max_level) return fail(MFMG_ERR_INVALID_ARG, "bad level");
-  const auto &lst = T.level_bricks[level];
-  *count = int64_t(lst.size());
-  for (size_t i = 0; i < lst.size(); ++i) {
-    int32_t b = lst[i];
-    if (coords)
-      for (int a = 0; a < 3; ++a) coords[3 * i + a] = T.coord[3 * int64_t(b) + a];
-    if (is_leaf) is_leaf[i] = b < T.n_leaf_bricks;
+  if (level < kMinLevel || level > h->co->tree->max_level)
+    return fail(MFMG_ERR_INVALID_ARG, "bad level");
+  try {
+    std::vector<int32_t> ids;
+    std::vector<BrickMeta> recs;
+    level_order(h, level, ids, recs, nullptr);
+    *count = int64_t(ids.size());
+    uint32_t nlb = h->co->dt->nlb;
+    for (size_t i = 0; i < ids.size(); ++i) {
+      if (coords)
+        for (int a = 0; a < 3; ++a) coords[3 * i + a] = recs[i].coord[a];
+      if (is_leaf) is_leaf[i] = uint32_t(ids[i]) < nlb;
+    }
+  } catch (const HipError &e) {
+    return hip_fail(e);
+  } catch (const std::bad_alloc &) {
+    return fail(MFMG_ERR_OOM, "host allocation failed");
   }
   return MFMG_OK;
 }
@@ -941,20 +982,21 @@ extern "C" mfmg_status mfmg_hierarchy_level_bricks(const mfmg_hierarchy *h, int 
 extern "C" mfmg_status mfmg_hierarchy_level_coeffs(const mfmg_hierarchy *h, int level,
                                                    double *out, void *stream) {
   if (!h || !out) return fail(MFMG_ERR_INVALID_ARG, "NULL argument");
-  if (!h->co->tree->on_host)
-    return fail(MFMG_ERR_INVALID_ARG, "needs an octree built on the host");
-  const Topology &T = h->co->tree->topo;
-  if (level < kMinLevel || level > T.max_level) return fail(MFMG_ERR_INVALID_ARG, "bad level");
+  if (level < kMinLevel || level > h->co->tree->max_level)
+    return fail(MFMG_ERR_INVALID_ARG, "bad level");
   hipStream_t s = (hipStream_t)stream;
   try {
-    const auto &lst = T.level_bricks[level];
-    for (size_t i = 0; i < lst.size(); ++i)
-      HIP_CHECK(hipMemcpyAsync(out + i * 256,
-                               h->coef64.p + int64_t(h->co->dt->perm[lst[i]]) * 256,
+    std::vector<int32_t> ids;
+    std::vector<BrickMeta> recs;
+    level_order(h, level, ids, recs, s);
+    for (size_t i = 0; i < ids.size(); ++i)
+      HIP_CHECK(hipMemcpyAsync(out + i * 256, h->coef64.p + int64_t(ids[i]) * 256,
                                256 * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIP_CHECK(hipStreamSynchronize(s));
   } catch (const HipError &e) {
     return hip_fail(e);
+  } catch (const std::bad_alloc &) {
+    return fail(MFMG_ERR_OOM, "host allocation failed");
   }
   return MFMG_OK;
 }

@@ -110,6 +110,25 @@ def test_solves_on_device_tables_are_identical(precision):
         assert np.array_equal(x, y)
 
 
+def test_level_accessors_on_device_tables():
+    """Per-level bricks and Algorithm 3 coefficients read back from a
+    hierarchy on the device-built octree equal those of the host-built one
+    (which the parity tests pin to the oracle)."""
+    from paper_2604_18886_amd import mfmg
+    case = Case(3, problems.config_spec(3, 4, 6))
+    td = mfmg.build_octree(case.spec, device=True)
+    hs = []
+    for tree in (case.tree, td):
+        co = mfmg.assemble_coeffs(tree, case.device(case.beta), case.bc, case.theta)
+        hs.append(mfmg.build_hierarchy(co, coarsest_level=3))
+    for level in range(3, 7):
+        ch, lh = hs[0].level_bricks(level)
+        cd, ld = hs[1].level_bricks(level)
+        assert np.array_equal(ch, cd) and np.array_equal(lh, ld)
+        assert np.array_equal(hs[0].level_coeffs(level).cpu().numpy(),
+                              hs[1].level_coeffs(level).cpu().numpy())
+
+
 def test_rebuilds_around_a_moving_sphere():
     """Time loop: each step rebuilds the octree on the device around the
     sphere's new position, re-assembles, re-coarsens and solves; the
