@@ -2,8 +2,8 @@
 level is its coarsest (the cycle is the coarsest smoother alone), cycle
 parameters other than the defaults (smoothing counts, coarsest level, the
 coarse-correction factor), a zero right-hand side, a domain that is almost
-all solid, a solve stopped by its iteration limit, and a right-hand side
-incompatible with a singular operator."""
+all solid, a domain with no active cell, a solve stopped by its iteration
+limit, and a right-hand side incompatible with a singular operator."""
 
 import numpy as np
 import pytest
@@ -171,3 +171,27 @@ def test_incompatible_right_hand_side():
     with pytest.raises(mfmg.MFMGError) as e:
         mfmg.pcg_solve_adjoint(h, p, case.device(bad), rtol=1e-10, null_space=0)
     assert e.value.status == mfmg.INCOMPATIBLE_RHS
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0, 1, 0, 0), (0,) * 6])
+def test_no_active_cell(bc):
+    """beta = 0 on every face: no leaf is a degree of freedom.  The forward
+    and adjoint solves return zeros with status OK (with and without a
+    Dirichlet wall, i.e. with the null-space shift on an empty active set)."""
+    import torch
+    from paper_2604_18886_amd import mfmg
+    spec = problems.config_spec(2, 3, 5)
+    base = Case(2, spec, bc=bc, theta=0.5)
+    case = Case(2, spec, bc=bc, theta=0.5, beta=np.zeros(base.disc.n_faces),
+                rhs=np.zeros(base.T.n))
+    assert not case.disc.active.any()
+    rng = np.random.default_rng(65)
+    rhs = rng.uniform(-1, 1, case.T.n)  # entries of inactive leaves are ignored
+    for precision in (mfmg.FP64, mfmg.MIXED):
+        h = _hierarchy(case, coarsest_level=3, precision=precision)
+        p, st = mfmg.pcg_solve(h, case.device(rhs), rtol=1e-10)
+        assert st["status"] == 0 and st["iters"] == 0
+        assert torch.count_nonzero(p).item() == 0
+        lam, g, st2 = mfmg.pcg_solve_adjoint(h, p, case.device(rhs), rtol=1e-10)
+        assert st2["status"] == 0
+        assert torch.count_nonzero(lam).item() == 0 and torch.count_nonzero(g).item() == 0
