@@ -295,6 +295,7 @@ def main():
     log(f"[bench] {nact} active leaves; coefficients + hierarchies in "
         f"{time.perf_counter() - t0:.1f} s")
     out = {}
+    sols = {}
     p = torch.empty_like(rhs_d)
     for name, h in hiers.items():
         for _ in range(args.warmup):
@@ -311,6 +312,7 @@ def main():
         ms_s, by_s = mfmg.profile(h, mfmg.PROFILE_SMOOTH, L, reps=50)
         ms_c, by_c = mfmg.profile(h, mfmg.PROFILE_CYCLE, 0, reps=10)
         ms_cp, by_cp = mfmg.profile(h, mfmg.PROFILE_COPY, 0, reps=20)
+        sols[name] = p.clone()
         # adjoint of L = ||p - p_t||^2 at this solution (outside the timed region)
         pn = p.cpu().numpy()
         pt = problems.adjoint_target(lev, ijk, np.abs(pn).max())
@@ -358,6 +360,10 @@ def main():
         f"assembly {rebuild['assemble_ms']:.1f} ms, mixed hierarchy "
         f"{rebuild['hierarchy_ms']:.1f} ms; total {rebuild['total_ms']:.1f} ms")
     head = out["mixed"]
+    mixed_vs_fp64 = float(torch.linalg.norm(sols["mixed"] - sols["fp64"]) /
+                          torch.linalg.norm(sols["fp64"]))
+    log(f"[bench] mixed vs FP64 solution: relative L2 difference {mixed_vs_fp64:.2e}")
+    del sols
     traffic = measured_traffic("mixed", L)
     roof = {"bound": "hbm", "achieved": head["smooth_gbs"], "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": head["smooth_gbs"] / HBM_PEAK_GBS,
@@ -400,6 +406,7 @@ def main():
                  "adjoint_ms": out["fp64"]["adjoint_ms"],
                  "adjoint_iters": out["fp64"]["adjoint_iters"]},
         "mixed": {"iters": head["iters"], "rel_resid_true": head["rel_resid_true"],
+                  "rel_l2_diff_vs_fp64": mixed_vs_fp64,
                   "vcycle_gbs": head["cycle_gbs"], "vcycle_ms": head["cycle_ms"],
                   "adjoint_ms": head["adjoint_ms"], "adjoint_iters": head["adjoint_iters"],
                   "wcycle_ms_per_solve": dt_w * 1e3, "wcycle_iters": stw["iters"]},
