@@ -160,6 +160,15 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _vec(t, n, what):
+    """Pointer to a float64 device vector of exactly n entries (the C ABI
+    cannot check the length of a device buffer, so the binding does)."""
+    torch = _torch()
+    if not (isinstance(t, torch.Tensor) and t.dtype == torch.float64 and t.numel() == n):
+        raise ValueError(f"{what}: expected a float64 device tensor of {n} entries")
+    return _ptr(t)
+
+
 # --------------------------------------------------------------------- octree
 class Octree:
     def __init__(self, handle):
@@ -269,11 +278,10 @@ def assemble_coeffs(tree, face_beta, bc=(DIRICHLET,) * 6, theta=0.5):
     """Leaf coefficients from per-face beta (device float64 tensor)."""
     torch = _torch()
     lib = load_library()
-    assert face_beta.dtype == torch.float64 and face_beta.numel() == tree.n_faces
     b = _BC((ctypes.c_int * 6)(*[int(x) for x in bc]), float(theta))
     h = _VP()
-    _check(lib.mfmg_assemble_coeffs(tree._h, _ptr(face_beta), ctypes.byref(b), _stream(),
-                                    ctypes.byref(h)))
+    _check(lib.mfmg_assemble_coeffs(tree._h, _vec(face_beta, tree.n_faces, "face_beta"),
+                                    ctypes.byref(b), _stream(), ctypes.byref(h)))
     return Coeffs(h, tree, bc, theta)
 
 
@@ -330,6 +338,7 @@ def pcg_solve(h, rhs, p=None, rtol=1e-10, max_iter=200, null_space=-1, history=F
     (device tensor) the iteration starts from that guess and stops at
     ||r|| <= rtol ||rhs||."""
     torch = _torch()
+    n = h.n_leaves
     if p is None:
         p = torch.empty_like(rhs)
     if x0 is not None:
@@ -337,7 +346,8 @@ def pcg_solve(h, rhs, p=None, rtol=1e-10, max_iter=200, null_space=-1, history=F
     sp = _SolveParams(float(rtol), int(max_iter), int(null_space), int(x0 is not None))
     st = SolveStats()
     hist = np.zeros(max_iter + 1) if history else None
-    status = _lib.mfmg_pcg_solve(h._h, _ptr(rhs), _ptr(p), ctypes.byref(sp), _stream(),
+    status = _lib.mfmg_pcg_solve(h._h, _vec(rhs, n, "rhs"), _vec(p, n, "p"),
+                                 ctypes.byref(sp), _stream(),
                                  ctypes.byref(st),
                                  hist.ctypes.data_as(_VP) if history else None)
     _check(status, allow_not_converged=True)
@@ -354,8 +364,10 @@ def pcg_solve_adjoint(h, p, dL_dp, rtol=1e-10, max_iter=200, null_space=-1):
     g = torch.empty(h.coeffs.tree.n_faces, dtype=torch.float64, device=dL_dp.device)
     sp = _SolveParams(float(rtol), int(max_iter), int(null_space), 0)
     st = SolveStats()
-    status = _lib.mfmg_pcg_solve_adjoint(h._h, _ptr(p), _ptr(dL_dp), _ptr(lam), _ptr(g),
-                                         ctypes.byref(sp), _stream(), ctypes.byref(st))
+    n = h.n_leaves
+    status = _lib.mfmg_pcg_solve_adjoint(h._h, _vec(p, n, "p"), _vec(dL_dp, n, "dL_dp"),
+                                         _ptr(lam), _ptr(g), ctypes.byref(sp), _stream(),
+                                         ctypes.byref(st))
     _check(status, allow_not_converged=True)
     return lam, g, st.as_dict()
 
@@ -365,21 +377,26 @@ def divergence(h, beta, u):
     """Integrated divergence (canonical leaf order) of face velocities u
     with face fluid fractions beta (device tensors, canonical face order)."""
     torch = _torch()
+    nf = h.coeffs.tree.n_faces
+    pb, pu = _vec(beta, nf, "beta"), _vec(u, nf, "u")
     div = torch.empty(h.n_leaves, dtype=torch.float64, device="cuda")
-    _check(_lib.mfmg_divergence(h._h, _ptr(beta), _ptr(u), _ptr(div), _stream()))
+    _check(_lib.mfmg_divergence(h._h, pb, pu, _ptr(div), _stream()))
     return div
 
 
 def project_velocity(h, beta, p, u):
     """u -= s F(p) / (beta h^2) in place (see mfmg_project_velocity)."""
-    _check(_lib.mfmg_project_velocity(h._h, _ptr(beta), _ptr(p), _ptr(u), _stream()))
+    nf = h.coeffs.tree.n_faces
+    _check(_lib.mfmg_project_velocity(h._h, _vec(beta, nf, "beta"), _vec(p, h.n_leaves, "p"),
+                                      _vec(u, nf, "u"), _stream()))
     return u
 
 
 def divergence_rms(h, div):
     """Volume-weighted RMS of div_i / V_i over the active leaves."""
     r = ctypes.c_double()
-    _check(_lib.mfmg_divergence_rms(h._h, _ptr(div), ctypes.byref(r), _stream()))
+    _check(_lib.mfmg_divergence_rms(h._h, _vec(div, h.n_leaves, "div"), ctypes.byref(r),
+                                    _stream()))
     return r.value
 
 
@@ -398,14 +415,16 @@ def project(h, beta, u, rtol=1e-10, max_iter=200):
 def apply_operator(h, x, transpose=False):
     torch = _torch()
     y = torch.empty_like(x)
-    _check(_lib.mfmg_apply_operator(h._h, _ptr(x), _ptr(y), int(transpose), _stream()))
+    _check(_lib.mfmg_apply_operator(h._h, _vec(x, h.n_leaves, "x"), _ptr(y), int(transpose),
+                                    _stream()))
     return y
 
 
 def apply_precond(h, r, transpose=False):
     torch = _torch()
     z = torch.empty_like(r)
-    _check(_lib.mfmg_apply_precond(h._h, _ptr(r), _ptr(z), int(transpose), _stream()))
+    _check(_lib.mfmg_apply_precond(h._h, _vec(r, h.n_leaves, "r"), _ptr(z), int(transpose),
+                                   _stream()))
     return z
 
 

@@ -66,3 +66,31 @@ def test_invalid_arguments_return_status():
     with pytest.raises(mfmg.MFMGError):
         mfmg.build_octree({"min_level": 3, "max_level": 4, "node_size": 4,
                            "prims": [{"kind": 7}]})
+
+
+def test_binding_rejects_wrong_vector_lengths():
+    """The C ABI cannot check the length of a device buffer: the binding
+    rejects a vector of the wrong length or type before any library call."""
+    import torch
+    from paper_2604_18886_amd import mfmg
+
+    class _Fake:  # stands in for a hierarchy: sizes only, never reaches the library
+        _h = None
+        n_leaves = 64
+
+        class coeffs:
+            class tree:
+                n_faces = 240
+
+    mfmg.load_library()
+    h = _Fake()
+    for bad in (torch.zeros(63, dtype=torch.float64), torch.zeros(64, dtype=torch.float32)):
+        with pytest.raises(ValueError):
+            mfmg.pcg_solve(h, bad)
+        with pytest.raises(ValueError):
+            mfmg.apply_operator(h, bad)
+        with pytest.raises(ValueError):
+            mfmg.divergence_rms(h, bad)
+    with pytest.raises(ValueError):
+        mfmg.divergence(h, torch.zeros(239, dtype=torch.float64),
+                        torch.zeros(240, dtype=torch.float64))
