@@ -660,25 +660,85 @@ __global__ void __launch_bounds__(kBlock) k_prolong(LevelArgs<V, CL, CI> A) {
 }
 
 // Coarsest level: nu RBGS iterations in one workgroup, (R,B) for the first
-// half of the iterations and (B,R) for the rest.
+// half of the iterations and (B,R) for the rest.  The level is a complete
+// grid of at most kCoarsestBricks bricks (no T-junctions), so its iterate
+// stays in LDS and each wave keeps the coefficients of its bricks (at most
+// kCoarsestSlots) in registers for all 2 nu half-sweeps; every value read,
+// and the order of every sum, is that of the global-memory half-sweep.
+constexpr int kCoarsestBricks = 64;
+constexpr int kCoarsestSlots = kCoarsestBricks / (1024 / kWave);
+
 template <class V, class CL, class CI>
 __global__ void __launch_bounds__(1024) k_coarsest(LevelArgs<V, CL, CI> A, int nu) {
   if (A.done && *A.done) return;
+  __shared__ V su[kCoarsestBricks * 64];
   const LaneC<V, CL> L = lane_consts<V, CL>();
   const LevelView<V, CL, CI> X = level_view(A);
-  uint32_t w = wave_id();
-  uint32_t nw = blockDim.x / kWave;
+  const uint32_t w = wave_id();
+  const uint32_t nw = blockDim.x / kWave;
+  const uint32_t n = A.R.n();
+  const int m = int(L.m);
+  V rhs[kCoarsestSlots], kown[kCoarsestSlots][3], kpl[kCoarsestSlots][3];
+  int32_t nbl[kCoarsestSlots][6];
+  uint64_t amask[kCoarsestSlots];
+#pragma unroll
+  for (int j = 0; j < kCoarsestSlots; ++j) {
+    uint32_t i = w + uint32_t(j) * nw;
+    if (i >= n) continue;
+    bool inner = i >= A.R.n_leaf;
+    uint32_t b = A.R.brick(i);
+    const BrickMeta M = load_meta(X.meta, b);
+    amask[j] = act_mask(M);
+    for (int a = 0; a < 3; ++a) {
+      kown[j][a] = inner ? own_coef<true>(X, b, 1 + a, L.m) : own_coef<false>(X, b, 1 + a, L.m);
+      kpl[j][a] = V(bload_bytes<CL>(X.pf, L.foff[a], b * uint32_t(48 * sizeof(CL))));
+    }
+    for (int d = 0; d < 6; ++d) {
+      int32_t nb = M.nbr[d];
+      nbl[j][d] = nb < 0 ? -1
+                  : uint32_t(nb) < X.nlb ? nb - int32_t(A.R.leaf_lo)
+                                          : int32_t(A.R.n_leaf) + nb - int32_t(A.R.inner_lo);
+    }
+    rhs[j] = bload<V>(X.b, L.m, b * 64u);
+    su[i * 64u + uint32_t(m)] = bload<V>(X.u, L.m, b * 64u);
+  }
+  __syncthreads();
   int half = nu / 2;
   for (int it = 0; it < nu; ++it) {
     for (int h2 = 0; h2 < 2; ++h2) {
       int colour = it < half ? h2 : 1 - h2;
-      for (uint32_t i = w; i < A.R.n(); i += nw) {
-        if (i < A.R.n_leaf) smooth_brick<false>(X, L, A.R.leaf_lo + i, colour);
-        else smooth_brick<true>(X, L, A.R.inner_lo + (i - A.R.n_leaf), colour);
+#pragma unroll
+      for (int j = 0; j < kCoarsestSlots; ++j) {
+        uint32_t i = w + uint32_t(j) * nw;
+        if (i >= n) continue;
+        V v[6], k[6];
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+          int a = d >> 1;
+          int p = L.p[d];
+          int32_t nbase = L.out[d] ? (nbl[j][d] >= 0 ? nbl[j][d] * 64 : -1) : int32_t(i) * 64;
+          v[d] = nbase >= 0 ? su[nbase + p] : V(0);
+          if (d & 1) {
+            V ks = shfl(kown[j][a], p);
+            k[d] = L.out[d] ? kpl[j][a] : ks;
+          } else {
+            k[d] = kown[j][a];
+          }
+        }
+        V c = ((k[0] + k[1]) + (k[2] + k[3])) + (k[4] + k[5]);
+        V S = V(0);
+#pragma unroll
+        for (int d = 0; d < 6; ++d) S += k[d] * v[d];
+        bool act = (amask[j] >> m) & 1ull;
+        if (act && L.colour == colour) su[i * 64u + uint32_t(m)] = div_by(rhs[j] + S, c);
       }
-      __threadfence_block();
       __syncthreads();
     }
+  }
+#pragma unroll
+  for (int j = 0; j < kCoarsestSlots; ++j) {
+    uint32_t i = w + uint32_t(j) * nw;
+    if (i < n) bstore<V>(X.u, L.m, A.R.brick(i) * 64u, su[i * 64u + uint32_t(m)]);
   }
 }
 
