@@ -59,6 +59,20 @@ __device__ __forceinline__ T shfl_xor(T v, int mask) {
   return __shfl_xor(v, mask, kWave);
 }
 
+// Value of v in the lane whose byte address (4 x lane) is addr.
+template <class T>
+__device__ __forceinline__ T bperm(T v, int addr) {
+  if constexpr (sizeof(T) == 8) {
+    uint64_t x = __builtin_bit_cast(uint64_t, v);
+    uint32_t lo = uint32_t(__builtin_amdgcn_ds_bpermute(addr, int(uint32_t(x))));
+    uint32_t hi = uint32_t(__builtin_amdgcn_ds_bpermute(addr, int(uint32_t(x >> 32))));
+    return __builtin_bit_cast(T, (uint64_t(hi) << 32) | lo);
+  } else {
+    static_assert(sizeof(T) == 4, "4- or 8-byte values");
+    return __builtin_bit_cast(T, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, v)));
+  }
+}
+
 // Sum over the 8 lanes of an aligned sibling group (identical in every lane:
 // the xor butterfly adds the same operands in every lane).
 template <class T>

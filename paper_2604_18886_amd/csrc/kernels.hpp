@@ -543,15 +543,139 @@ __device__ __forceinline__ void smooth_brick(const LevelView<V, CL, CI, CP> &X, 
   if (act && L.colour == colour) bstore<V>(X.u, L.m, b * 64u, div_by(rhs + S, c));
 }
 
+// Gathered face loads of an FP64 colour-c half-sweep.  The loads of the
+// stencil are limited by the texture units' per-lane work, and the six face
+// loads of stencil_sum are full-wave loads of which only the face lanes are
+// in range.  The brick's colour-c cells on its six faces need 48 values from
+// the neighbouring bricks (8 per face); lane k = 8 d + j (k < 48) fetches the
+// one for the j-th such cell of face d in a single load and each cell takes
+// its value from that lane with a lane exchange.  Likewise one load brings
+// the brick's 48 plus-face coefficients (lane k: entry k).  A face's cells
+// are numbered by their face index f (dev_face_index); cells f = 2j and
+// 2j + 1 have opposite colours, and the colour-c one is the j-th.  (For FP32
+// the exchanges cost more than the loads they save, and the six face loads
+// stay.)
+struct HalfGather {
+  uint32_t goff;   // k < 48: byte offset of lane k's value in the brick across face k / 8
+  int gdir;        // k / 8 for k < 48, 6 (no load) otherwise
+  int gsrc[6];     // 4 x the lane holding the value across face d for the lane's cell
+  int psrc[6];     // 4 x the lane's partner lane across direction d
+  uint32_t pfoff;  // k < 48: byte offset of plus-face entry k, else out of range
+  int pfsrc[3];    // 4 x the lane holding the lane's plus-face entry of axis a
+};
+
+template <class V, class CL>
+__device__ __forceinline__ HalfGather half_gather(const LaneC<V, CL> &L, int colour) {
+  HalfGather G;
+  int k = int(L.m);
+  G.gdir = k < 48 ? k >> 3 : 6;
+  G.goff = kOutOfRange;
+  if (k < 48) {
+    int d = k >> 3, a = d >> 1;
+    int o0 = a == 0 ? 1 : 0;
+    int o1 = a == 2 ? 1 : 2;
+    int side = (d & 1) ? 3 : 0;
+    int f = 2 * (k & 7);
+    if (((side + (f & 3) + (f >> 2)) & 1) != colour) f += 1;
+    int xyz[3];
+    xyz[a] = side;
+    xyz[o0] = f & 3;
+    xyz[o1] = f >> 2;
+    int p = dev_partner(dev_morton(xyz[0], xyz[1], xyz[2]), d);
+    G.goff = uint32_t(p) * uint32_t(sizeof(V));
+  }
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    G.gsrc[d] = 4 * (8 * d + (dev_face_index(k, d >> 1) >> 1));
+    G.psrc[d] = 4 * L.p[d];
+  }
+  G.pfoff = k < 48 ? uint32_t(k) * uint32_t(sizeof(CL)) : kOutOfRange;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) G.pfsrc[a] = 4 * (a * 16 + dev_face_index(k, a));
+  return G;
+}
+
+// One brick of a colour half-sweep with gathered face loads: the values,
+// ghosts and sums of smooth_brick, term for term.
+template <bool INNER, class V, class CL, class CI, int CP>
+__device__ __forceinline__ void smooth_brick_gathered(const LevelView<V, CL, CI, CP> &X,
+                                                      const LaneC<V, CL> &L, const HalfGather &G,
+                                                      uint32_t b, int colour) {
+  const BrickMeta M = load_meta(X.meta, b);
+  V k0 = own_coef<INNER>(X, b, 1, L.m);
+  V k1 = own_coef<INNER>(X, b, 2, L.m);
+  V k2 = own_coef<INNER>(X, b, 3, L.m);
+  V u = bload<V>(X.u, L.m, b * 64u);
+  V rhs = bload<V, CP>(X.b, L.m, b * 64u);
+  uint32_t gb = 0u;  // byte offset of the brick across the lane's gather face
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    uint32_t sb = M.nbr[d] >= 0 ? uint32_t(M.nbr[d]) * uint32_t(64 * sizeof(V)) : kOutOfRange;
+    gb = G.gdir == d ? sb : gb;
+  }
+  V gv = bload_bytes<V>(X.u, G.goff + gb, 0);
+  CL pfv = bload_bytes<CL, CP>(X.pf, G.pfoff, b * uint32_t(48 * sizeof(CL)));
+  V v[6], k[6];
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    int a = d >> 1;
+    V kown = a == 0 ? k0 : (a == 1 ? k1 : k2);
+    V vl = bperm(gv, G.gsrc[d]);
+    V vs = bperm(u, G.psrc[d]);
+    v[d] = L.out[d] ? vl : vs;
+    if (d & 1) {
+      V kl = V(bperm(pfv, G.pfsrc[a]));
+      V ks = bperm(kown, G.psrc[d]);
+      k[d] = L.out[d] ? kl : ks;
+    } else {
+      k[d] = kown;
+    }
+  }
+  if (M.flags & kFlagT) {
+    uint64_t amask = act_mask(M);
+    bool act = (amask >> L.m) & 1ull;
+    V s = group8_sum(act ? u : V(0));
+    int cnt = __popcll((amask >> (L.m & 56u)) & 0xffull);
+    V ubar = cnt ? s / V(cnt) : V(0);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      if ((M.flags >> d) & 1u) {
+        uint32_t J = uint32_t(dev_decode_coarse(M.nbr[d]));
+        const BrickMeta MJ = load_meta(X.meta, J);
+        V uJ = bload<V>(X.u, uint32_t(coarse_local(M, int(L.m), d, MJ)), J * 64u);
+        V g = u + (uJ - ubar) * V(0.5);
+        v[d] = L.out[d] ? g : v[d];
+      }
+    }
+  }
+  V c = ((k[0] + k[1]) + (k[2] + k[3])) + (k[4] + k[5]);
+  V S = V(0);
+#pragma unroll
+  for (int d = 0; d < 6; ++d) S += k[d] * v[d];
+  bool act = (act_mask(M) >> L.m) & 1ull;
+  if (act && L.colour == colour) bstore<V>(X.u, L.m, b * 64u, div_by(rhs + S, c));
+}
+
 template <class V, class CL, class CI, int CP = kCpolDefault>
 __global__ void __launch_bounds__(kBlock) k_smooth(LevelArgs<V, CL, CI> A, int colour) {
   if (A.done && *A.done) return;
-  const LaneC<V, CL> L = lane_consts<V, CL>();
-  const LevelView<V, CL, CI, CP> X = level_view<CP>(A);
-  const WaveLoop W = wave_loop(A.R.n());
-  for (uint32_t i = W.first; i < W.end; i += W.step) {
-    if (i < A.R.n_leaf) smooth_brick<false>(X, L, A.R.leaf_lo + i, colour);
-    else smooth_brick<true>(X, L, A.R.inner_lo + (i - A.R.n_leaf), colour);
+  if constexpr (sizeof(V) == 8) {
+    const LaneC<V, CL> L = lane_consts<V, CL>();
+    const HalfGather G = half_gather(L, colour);
+    const LevelView<V, CL, CI, CP> X = level_view<CP>(A);
+    const WaveLoop W = wave_loop(A.R.n());
+    for (uint32_t i = W.first; i < W.end; i += W.step) {
+      if (i < A.R.n_leaf) smooth_brick_gathered<false>(X, L, G, A.R.leaf_lo + i, colour);
+      else smooth_brick_gathered<true>(X, L, G, A.R.inner_lo + (i - A.R.n_leaf), colour);
+    }
+  } else {
+    const LaneC<V, CL> L = lane_consts<V, CL>();
+    const LevelView<V, CL, CI, CP> X = level_view<CP>(A);
+    const WaveLoop W = wave_loop(A.R.n());
+    for (uint32_t i = W.first; i < W.end; i += W.step) {
+      if (i < A.R.n_leaf) smooth_brick<false>(X, L, A.R.leaf_lo + i, colour);
+      else smooth_brick<true>(X, L, A.R.inner_lo + (i - A.R.n_leaf), colour);
+    }
   }
 }
 

@@ -78,12 +78,13 @@ inline unsigned grid_for(int64_t bricks) {
 // Grid of the level kernels (wave_loop): a multiple of 8 workgroups, at
 // most waves_per_xcd waves per XCD, each looping over its share of bricks.
 // Measured on the finest level of the large workload: the FP32 stencils are
-// fastest with 2048 waves per XCD looping, the FP64 ones (more registers,
-// fewer waves resident) with one brick per wave.  Reductions over the
-// leaves keep the 2048 cap, so that one workgroup adds their partials.
+// fastest with 2048 waves per XCD looping; the FP64 ones (more registers,
+// five waves resident per SIMD) with 1920, three rounds of them (FP64
+// half-sweep 207 -> 192 us against one brick per wave).  Reductions over
+// the leaves keep the 2048 cap, so that one workgroup adds their partials.
 // MFMG_WAVES_PER_XCD (read once) overrides the cap, for tuning.
 constexpr int64_t kWavesPerXcd32 = 2048;
-constexpr int64_t kWavesPerXcd64 = int64_t(1) << 30;
+constexpr int64_t kWavesPerXcd64 = 1920;
 inline int64_t waves_override() {
   static const int64_t v = [] {
     const char *e = std::getenv("MFMG_WAVES_PER_XCD");
