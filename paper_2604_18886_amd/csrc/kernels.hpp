@@ -360,6 +360,13 @@ struct LaneC {
   uint32_t poff[6];  // out[d] ? p * sizeof(V) : kOutOfRange
   uint32_t foff[3];  // plus-face slot of the cell on axis a, in bytes
   int colour;        // (x + y + z) & 1
+  // FP64 only: gathered face loads of the full stencil (see stencil_sum)
+  uint32_t goff[2];  // lane k < 48 of gather h: byte offset of its value in the brick
+  int gdir[2];       //   across face 3h + k / 16 (that face; 6 for k >= 48)
+  int gsrc[6];       // 4 x the lane holding the value across face d (gather d / 3)
+  int psrc[6];       // 4 x p[d]
+  uint32_t pfoff;    // lane k < 48: byte offset of plus-face entry k
+  int pfsrc[3];      // 4 x the lane holding the lane's plus-face entry of axis a
 };
 
 template <class V, class CL>
@@ -377,6 +384,34 @@ __device__ __forceinline__ LaneC<V, CL> lane_consts() {
   for (int a = 0; a < 3; ++a)
     L.foff[a] = uint32_t(a * 16 + dev_face_index(m, a)) * uint32_t(sizeof(CL));
   L.colour = (dev_cx(m) + dev_cy(m) + dev_cz(m)) & 1;
+  if constexpr (sizeof(V) == 8) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      L.gdir[h] = 6;
+      L.goff[h] = kOutOfRange;
+      if (m < 48) {
+        int d = 3 * h + (m >> 4), a = d >> 1;
+        int o0 = a == 0 ? 1 : 0;
+        int o1 = a == 2 ? 1 : 2;
+        int f = m & 15;
+        int xyz[3];
+        xyz[a] = (d & 1) ? 3 : 0;
+        xyz[o0] = f & 3;
+        xyz[o1] = f >> 2;
+        L.gdir[h] = d;
+        L.goff[h] = uint32_t(dev_partner(dev_morton(xyz[0], xyz[1], xyz[2]), d)) *
+                    uint32_t(sizeof(V));
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      L.gsrc[d] = 4 * (16 * (d % 3) + dev_face_index(m, d >> 1));
+      L.psrc[d] = 4 * L.p[d];
+    }
+    L.pfoff = m < 48 ? uint32_t(m) * uint32_t(sizeof(CL)) : kOutOfRange;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) L.pfsrc[a] = 4 * (a * 16 + dev_face_index(m, a));
+  }
   return L;
 }
 
@@ -495,12 +530,55 @@ __device__ __forceinline__ void face_values(__amdgpu_buffer_rsrc_t x, __amdgpu_b
   }
 }
 
+// FP64 form of face_values: the brick's 96 face cells take their values
+// from two gathered loads (lane k < 48 of gather h fetches the value across
+// face 3h + k / 16 for the face cell with face index k % 16) and its 48
+// plus-face coefficients from one (lane k: entry k), each cell reading its
+// entries by lane exchange.  The face loads of face_values are full-wave
+// loads with only the face lanes in range; for 8-byte values the texture
+// units' per-lane work on them, not HBM, bounded the stencils.
+template <int CP, class V, class CL>
+__device__ __forceinline__ void face_values_gathered(__amdgpu_buffer_rsrc_t x,
+                                                     __amdgpu_buffer_rsrc_t pf,
+                                                     const LaneC<V, CL> &L, uint32_t b,
+                                                     const BrickMeta &M, V u, V k0, V k1, V k2,
+                                                     V (&v)[6], V (&k)[6]) {
+  uint32_t gb0 = 0u, gb1 = 0u;  // bytes to the brick across each gather's face
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    uint32_t sb = M.nbr[d] >= 0 ? uint32_t(M.nbr[d]) * uint32_t(64 * sizeof(V)) : kOutOfRange;
+    gb0 = L.gdir[0] == d ? sb : gb0;
+    gb1 = L.gdir[1] == d ? sb : gb1;
+  }
+  V g0 = bload_bytes<V>(x, L.goff[0] + gb0, 0);
+  V g1 = bload_bytes<V>(x, L.goff[1] + gb1, 0);
+  CL pfv = bload_bytes<CL, CP>(pf, L.pfoff, b * uint32_t(48 * sizeof(CL)));
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    int a = d >> 1;
+    V kown = a == 0 ? k0 : (a == 1 ? k1 : k2);
+    V vl = bperm(d < 3 ? g0 : g1, L.gsrc[d]);
+    V vs = bperm(u, L.psrc[d]);
+    v[d] = L.out[d] ? vl : vs;
+    if (d & 1) {
+      V kl = V(bperm(pfv, L.pfsrc[a]));
+      V ks = bperm(kown, L.psrc[d]);
+      k[d] = L.out[d] ? kl : ks;
+    } else {
+      k[d] = kown;
+    }
+  }
+}
+
 template <class V, class CL, class CI, int CP>
 __device__ __forceinline__ V stencil_sum(const LevelView<V, CL, CI, CP> &X, const LaneC<V, CL> &L,
                                          uint32_t b, const BrickMeta &M, V u, V k0, V k1,
                                          V k2, V &diag) {
   V v[6], k[6];
-  face_values<CP>(X.u, X.pf, L, b, M, u, k0, k1, k2, v, k);
+  if constexpr (sizeof(V) == 8)
+    face_values_gathered<CP>(X.u, X.pf, L, b, M, u, k0, k1, k2, v, k);
+  else
+    face_values<CP>(X.u, X.pf, L, b, M, u, k0, k1, k2, v, k);
   if (M.flags & kFlagT) {
     uint64_t amask = act_mask(M);
     bool act = (amask >> L.m) & 1ull;

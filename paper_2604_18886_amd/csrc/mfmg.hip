@@ -108,6 +108,14 @@ inline unsigned stencil_grid(int64_t bricks) {
   if (waves_override()) return grid_waves(bricks, waves_override());
   return grid_waves(bricks, sizeof(V) == 8 ? kWavesPerXcd64 : kWavesPerXcd32);
 }
+// The transposed cycle's stencils (adjoint solves) keep one brick per wave
+// in FP64: they do not use the gathered face loads, and looping made them
+// slower.
+template <class V>
+inline unsigned stencil_grid_T(int64_t bricks) {
+  if (waves_override()) return grid_waves(bricks, waves_override());
+  return grid_waves(bricks, sizeof(V) == 8 ? int64_t(1) << 30 : kWavesPerXcd32);
+}
 // A stencil launch whose single-use streams (coefficients, plus faces,
 // right-hand side) and iterate together exceed the 256 MB Infinity Cache
 // gains nothing from caching those streams for the next launch, and they
@@ -1178,10 +1186,10 @@ struct CycleT {
     A.W = win;
     A.W2 = wout ? wout : win;
     if (h->stream_lv[size_t(l)])
-      hipLaunchKernelGGL((k_T_apply<V, CL, CI, kCpolStream>), dim3(stencil_grid<V>(A.R.n())),
+      hipLaunchKernelGGL((k_T_apply<V, CL, CI, kCpolStream>), dim3(stencil_grid_T<V>(A.R.n())),
                          dim3(kBlock), 0, s, A, colour, next);
     else
-      hipLaunchKernelGGL((k_T_apply<V, CL, CI>), dim3(stencil_grid<V>(A.R.n())), dim3(kBlock),
+      hipLaunchKernelGGL((k_T_apply<V, CL, CI>), dim3(stencil_grid_T<V>(A.R.n())), dim3(kBlock),
                          0, s, A, colour, next);
     if (l > h->lc) {
       auto C = args(l - 1, 1);
@@ -1203,10 +1211,10 @@ struct CycleT {
     if (!w_ready) {
       A.W = W2;
       if (h->stream_lv[size_t(l)])
-        hipLaunchKernelGGL((k_T_sweep_w<V, CL, CI, kCpolStream>), dim3(stencil_grid<V>(A.R.n())),
+        hipLaunchKernelGGL((k_T_sweep_w<V, CL, CI, kCpolStream>), dim3(stencil_grid_T<V>(A.R.n())),
                            dim3(kBlock), 0, s, A, first);
       else
-        hipLaunchKernelGGL((k_T_sweep_w<V, CL, CI>), dim3(stencil_grid<V>(A.R.n())),
+        hipLaunchKernelGGL((k_T_sweep_w<V, CL, CI>), dim3(stencil_grid_T<V>(A.R.n())),
                            dim3(kBlock), 0, s, A, first);
     }
     V *buf[2] = {W2, W};
@@ -1232,7 +1240,7 @@ struct CycleT {
     for (int k = 0; k < p.mu; ++k) fas_T(l - 1);
     auto C = args(l - 1, 0);
     hipLaunchKernelGGL((k_T_coarse<V, CL, CI>), dim3(grid_for(C.R.n())), dim3(kBlock), 0, s, C);
-    hipLaunchKernelGGL((k_T_fas<V, CL, CI>), dim3(stencil_grid<V>(C.R.n())), dim3(kBlock), 0,
+    hipLaunchKernelGGL((k_T_fas<V, CL, CI>), dim3(stencil_grid_T<V>(C.R.n())), dim3(kBlock), 0,
                        s, C);
     hipLaunchKernelGGL((k_T_prolong<V, CL, CI>), dim3(grid_for(A.R.n())), dim3(kBlock), 0, s,
                        A);
