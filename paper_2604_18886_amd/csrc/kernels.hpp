@@ -944,6 +944,252 @@ __global__ void __launch_bounds__(1024) k_coarsest(LevelArgs<V, CL, CI> A, int n
   }
 }
 
+// The FAS step of level f = lc + 1 in one workgroup (Algorithm 4 on that
+// level: FAS right-hand side, pre-smoothing, residual restriction, mu
+// coarsest solves, prolongation, post-smoothing) when level f is a complete
+// grid of at most kCoarsestBricks bricks without T-junctions and the
+// coarsest level has at most kBottomCoarse bricks.  Both iterates stay in
+// LDS and each wave keeps the coefficients of its bricks in registers, so
+// the dozen launches of a few microseconds each that the separate kernels
+// take become one.  Every value read and the order of every sum are those
+// of k_fas_rhs, k_smooth, k_restrict, k_coarsest and k_prolong, and the
+// arrays in memory end as those kernels leave them.  fas = 0 skips the FAS
+// right-hand side (a W-cycle's second visit: it is already in B).
+constexpr int kBottomCoarse = 1024 / kWave;
+
+// Six local neighbour indices in [-1, 62] packed as bytes (-1: wall).
+__device__ __forceinline__ uint64_t pack_nbr(const BrickMeta &M, const Range &R, uint32_t nlb) {
+  uint64_t v = 0;
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    int32_t nb = M.nbr[d];
+    int32_t loc = nb < 0 ? -1
+                  : uint32_t(nb) < nlb ? nb - int32_t(R.leaf_lo)
+                                       : int32_t(R.n_leaf) + nb - int32_t(R.inner_lo);
+    v |= uint64_t(uint8_t(int8_t(loc))) << (8 * d);
+  }
+  return v;
+}
+__device__ __forceinline__ int32_t unpack_nbr(uint64_t v, int d) {
+  return int32_t(int8_t(uint8_t(v >> (8 * d))));
+}
+
+template <class V, class CL, class CI>
+__global__ void __launch_bounds__(1024) k_bottom(LevelArgs<V, CL, CI> Af, LevelArgs<V, CL, CI> Ac,
+                                                 int nu_pre, int nu_post, int nu_coarse, int mu,
+                                                 int fas, V scale) {
+  if (Af.done && *Af.done) return;
+  __shared__ V uf[kCoarsestBricks * 64];  // iterate of level f
+  __shared__ V uc[kBottomCoarse * 64];    // iterate of the coarsest level
+  __shared__ V bc[kBottomCoarse * 64];    // restricted residual of its inner cells
+  __shared__ V sc[kBottomCoarse * 64];    // u* of its inner cells
+  const LaneC<V, CL> L = lane_consts<V, CL>();
+  const LevelView<V, CL, CI> Xf = level_view(Af);
+  const LevelView<V, CL, CI> Xc = level_view(Ac);
+  const uint32_t w = wave_id();
+  const uint32_t nw = blockDim.x / kWave;
+  const uint32_t nf = Af.R.n(), nc = Ac.R.n();
+  const uint32_t m = L.m;
+  V rf[kCoarsestSlots], kf[kCoarsestSlots][3], pf[kCoarsestSlots][3];
+  uint64_t nbf[kCoarsestSlots];    // packed local neighbour indices
+  uint64_t af[kCoarsestSlots];
+  uint32_t parf[kCoarsestSlots];  // 64 x (parent's local index) + 8 x octant
+#pragma unroll
+  for (int j = 0; j < kCoarsestSlots; ++j) {
+    uint32_t i = w + uint32_t(j) * nw;
+    if (i >= nf) continue;
+    bool inner = i >= Af.R.n_leaf;
+    uint32_t b = Af.R.brick(i);
+    const BrickMeta M = load_meta(Xf.meta, b);
+    af[j] = act_mask(M);
+    for (int a = 0; a < 3; ++a) {
+      kf[j][a] = inner ? own_coef<true>(Xf, b, 1 + a, m) : own_coef<false>(Xf, b, 1 + a, m);
+      pf[j][a] = V(bload_bytes<CL>(Xf.pf, L.foff[a], b * uint32_t(48 * sizeof(CL))));
+    }
+    nbf[j] = pack_nbr(M, Af.R, Xf.nlb);
+    parf[j] = (Ac.R.n_leaf + uint32_t(M.parent) - Ac.R.inner_lo) * 64u +
+              uint32_t(octant_of(M)) * 8u;
+    rf[j] = bload<V>(Xf.b, m, b * 64u);
+    uf[i * 64u + m] = bload<V>(Xf.u, m, b * 64u);
+  }
+  // the coarsest level: coefficients (loaded now, used after the
+  // restriction); its leaf bricks keep their iterate and right-hand side
+  V rc = V(0);
+  V kc[3], pc[3];
+  uint64_t nbc = 0;
+  uint64_t ac = 0;
+  bool cin = false;
+  if (w < nc) {
+    cin = w >= Ac.R.n_leaf;
+    uint32_t b = Ac.R.brick(w);
+    const BrickMeta M = load_meta(Xc.meta, b);
+    ac = act_mask(M);
+    for (int a = 0; a < 3; ++a) {
+      kc[a] = cin ? own_coef<true>(Xc, b, 1 + a, m) : own_coef<false>(Xc, b, 1 + a, m);
+      pc[a] = V(bload_bytes<CL>(Xc.pf, L.foff[a], b * uint32_t(48 * sizeof(CL))));
+    }
+    nbc = pack_nbr(M, Ac.R, Xc.nlb);
+    if (!cin) {
+      rc = bload<V>(Xc.b, m, b * 64u);
+      uc[w * 64u + m] = bload<V>(Xc.u, m, b * 64u);
+    }
+  }
+  __syncthreads();
+
+  // neighbour sum and diagonal of slot j of level f from the LDS iterate
+  auto stencil_f = [&](int j, uint32_t i, V &c) {
+    V v[6], k[6];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      int a = d >> 1;
+      int p = L.p[d];
+      int32_t nl = unpack_nbr(nbf[j], d);
+      int32_t nbase = L.out[d] ? (nl >= 0 ? nl * 64 : -1) : int32_t(i) * 64;
+      v[d] = nbase >= 0 ? uf[nbase + p] : V(0);
+      if (d & 1) {
+        V ks = shfl(kf[j][a], p);
+        k[d] = L.out[d] ? pf[j][a] : ks;
+      } else {
+        k[d] = kf[j][a];
+      }
+    }
+    c = ((k[0] + k[1]) + (k[2] + k[3])) + (k[4] + k[5]);
+    V S = V(0);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) S += k[d] * v[d];
+    return S;
+  };
+  auto half_sweep_f = [&](int colour) {
+#pragma unroll
+    for (int j = 0; j < kCoarsestSlots; ++j) {
+      uint32_t i = w + uint32_t(j) * nw;
+      if (i >= nf) continue;
+      V c;
+      V S = stencil_f(j, i, c);
+      bool act = (af[j] >> m) & 1ull;
+      if (act && L.colour == colour) uf[i * 64u + m] = div_by(rf[j] + S, c);
+    }
+    __syncthreads();
+  };
+
+  // FAS right-hand side of the inner bricks: b += A u*
+  if (fas) {
+#pragma unroll
+    for (int j = 0; j < kCoarsestSlots; ++j) {
+      uint32_t i = w + uint32_t(j) * nw;
+      if (i >= nf || i < Af.R.n_leaf) continue;
+      V c;
+      V S = stencil_f(j, i, c);
+      V u = uf[i * 64u + m];
+      bool act = (af[j] >> m) & 1ull;
+      rf[j] = act ? rf[j] + (c * u - S) : V(0);
+      bstore<V>(Xf.b, m, Af.R.brick(i) * 64u, rf[j]);
+    }
+    __syncthreads();  // every wave's reads of uf before the first writes
+  }
+  for (int it = 0; it < nu_pre; ++it) {
+    half_sweep_f(0);
+    half_sweep_f(1);
+  }
+  // residual restriction and u* to the coarsest level
+#pragma unroll
+  for (int j = 0; j < kCoarsestSlots; ++j) {
+    uint32_t i = w + uint32_t(j) * nw;
+    if (i >= nf) continue;
+    V c;
+    V S = stencil_f(j, i, c);
+    V u = uf[i * 64u + m];
+    bool act = (af[j] >> m) & 1ull;
+    V r = act ? rf[j] - (c * u - S) : V(0);
+    V rs = group8_sum(r);
+    V us = group8_sum(act ? u : V(0));
+    int cnt = __popcll((af[j] >> (m & 56u)) & 0xffull);
+    if ((m & 7u) == 0) {
+      uint32_t q = parf[j] + (m >> 3);
+      V ust = cnt ? div_by(us, V(cnt)) : V(0);
+      bc[q] = rs * scale;
+      uc[q] = ust;
+      sc[q] = ust;
+    }
+  }
+  __syncthreads();
+
+  // the coarsest level: FAS right-hand side, mu solves
+  auto stencil_c = [&](V &c) {
+    V v[6], k[6];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      int a = d >> 1;
+      int p = L.p[d];
+      int32_t nl = unpack_nbr(nbc, d);
+      int32_t nbase = L.out[d] ? (nl >= 0 ? nl * 64 : -1) : int32_t(w) * 64;
+      v[d] = nbase >= 0 ? uc[nbase + p] : V(0);
+      if (d & 1) {
+        V ks = shfl(kc[a], p);
+        k[d] = L.out[d] ? pc[a] : ks;
+      } else {
+        k[d] = kc[a];
+      }
+    }
+    c = ((k[0] + k[1]) + (k[2] + k[3])) + (k[4] + k[5]);
+    V S = V(0);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) S += k[d] * v[d];
+    return S;
+  };
+  if (w < nc && cin) {
+    V c;
+    V S = stencil_c(c);
+    V u = uc[w * 64u + m];
+    bool act = (ac >> m) & 1ull;
+    rc = act ? bc[w * 64u + m] + (c * u - S) : V(0);
+  }
+  __syncthreads();
+  int half = nu_coarse / 2;
+  for (int rep = 0; rep < mu; ++rep)
+    for (int it = 0; it < nu_coarse; ++it)
+      for (int h2 = 0; h2 < 2; ++h2) {
+        int colour = it < half ? h2 : 1 - h2;
+        if (w < nc) {
+          V c;
+          V S = stencil_c(c);
+          bool act = (ac >> m) & 1ull;
+          if (act && L.colour == colour) uc[w * 64u + m] = div_by(rc + S, c);
+        }
+        __syncthreads();
+      }
+
+  // prolongation of the correction, post-smoothing
+#pragma unroll
+  for (int j = 0; j < kCoarsestSlots; ++j) {
+    uint32_t i = w + uint32_t(j) * nw;
+    if (i >= nf) continue;
+    uint32_t q = parf[j] + (m >> 3);
+    V corr = uc[q] - sc[q];
+    if ((af[j] >> m) & 1ull) uf[i * 64u + m] = uf[i * 64u + m] + corr;
+  }
+  __syncthreads();
+  for (int it = 0; it < nu_post; ++it) {
+    half_sweep_f(1);
+    half_sweep_f(0);
+  }
+
+  // the arrays as the separate kernels leave them
+#pragma unroll
+  for (int j = 0; j < kCoarsestSlots; ++j) {
+    uint32_t i = w + uint32_t(j) * nw;
+    if (i < nf) bstore<V>(Xf.u, m, Af.R.brick(i) * 64u, uf[i * 64u + m]);
+  }
+  if (w < nc) {
+    uint32_t b = Ac.R.brick(w);
+    bstore<V>(Xc.u, m, b * 64u, uc[w * 64u + m]);
+    if (cin) {
+      bstore<V>(Xc.b, m, b * 64u, rc);
+      bstore<V>(Xc.us, m, (b - Xc.nlb) * 64u, sc[w * 64u + m]);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // transpose of the cycle (adjoint solves).  The cycle's linear steps are
 // transposed and taken in reverse order; this gives a cycle for A^T in
@@ -1009,7 +1255,10 @@ __device__ __forceinline__ V level_AuT(const LevelViewT<V, CL, CI, CP> &X, const
   V k1 = own_coef<INNER>(X.c, b, 2, L.m);
   V k2 = own_coef<INNER>(X.c, b, 3, L.m);
   V v[6], k[6];
-  face_values<CP>(X.w, X.c.pf, L, b, M, w, k0, k1, k2, v, k);
+  if constexpr (sizeof(V) == 8)
+    face_values_gathered<CP>(X.w, X.c.pf, L, b, M, w, k0, k1, k2, v, k);
+  else
+    face_values<CP>(X.w, X.c.pf, L, b, M, w, k0, k1, k2, v, k);
   V c = ((k[0] + k[1]) + (k[2] + k[3])) + (k[4] + k[5]);
   diag = c;
   uint64_t amask = act_mask(M);

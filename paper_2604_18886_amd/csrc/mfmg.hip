@@ -192,6 +192,7 @@ struct mfmg_hierarchy {
   double n_active = 0;     // active leaf cells
   std::vector<char> stream_lv;  // per level: the cycle's stencils stream their coefficients
   bool stream_composite = false;  // the same for the composite operator
+  bool fuse_bottom = false;       // level lc + 1 and the coarsest level in one kernel (k_bottom)
   // work vectors (device order)
   DevBuf<double> U64, B64, S64;  // FP64 cycle: nb*64, nb*64, (nb-nlb)*64
   DevBuf<float> U32, B32, S32;   // mixed cycle
@@ -918,6 +919,31 @@ extern "C" mfmg_status mfmg_build_hierarchy(const mfmg_coeffs *co, const mfmg_mg
       }
       h->stream_composite = double(nlb) * (64 * (2 * 8.0 + 3.75 * 8.0) + 64) > stream_threshold();
     }
+    {
+      // k_bottom takes level lc + 1 (below the finest) and the coarsest
+      // level when the former is a grid of at most kCoarsestBricks bricks
+      // without T-junctions and the latter has at most kBottomCoarse bricks.
+      // MFMG_FUSE_BOTTOM=0 (read at each build) keeps the separate kernels.
+      const char *e = std::getenv("MFMG_FUSE_BOTTOM");
+      int f = h->lc + 1;
+      bool ok = !(e && e[0] == '0') && f < h->L && D.range[f].n() <= uint32_t(kCoarsestBricks) &&
+                D.range[h->lc].n() <= uint32_t(kBottomCoarse);
+      if (ok) {
+        const Range &R = D.range[f];
+        for (uint32_t i = 0; i < R.n_leaf; ++i)
+          if (mh[R.leaf_lo + i].flags & kFlagT) ok = false;
+        std::vector<BrickMeta> mi(R.n_inner);
+        if (R.n_inner) {
+          HIP_CHECK(hipMemcpyAsync(mi.data(), h->meta.p + R.inner_lo,
+                                   size_t(R.n_inner) * sizeof(BrickMeta), hipMemcpyDeviceToHost,
+                                   s));
+          HIP_CHECK(hipStreamSynchronize(s));
+        }
+        for (const BrickMeta &M : mi)
+          if (M.flags & kFlagT) ok = false;
+      }
+      h->fuse_bottom = ok;
+    }
     *out = h.release();
   } catch (const HipError &e) {
     return hip_fail(e);
@@ -1100,12 +1126,19 @@ struct Cycle {
     else
       hipLaunchKernelGGL((k_restrict<V, CL, CI>), dim3(stencil_grid<V>(A.R.n())), dim3(kBlock),
                          0, s, A, scale);
-    auto C = args(l - 1, true);
-    if (C.R.n())
-      hipLaunchKernelGGL((k_fas_rhs<V, CL, CI>), dim3(stencil_grid<V>(C.R.n_inner)),
-                         dim3(kBlock), 0,
-                         s, C);
-    for (int k = 0; k < p.mu; ++k) fas(l - 1);
+    if (l - 1 == h->lc + 1 && h->fuse_bottom) {
+      auto F = args(l - 1, false);
+      auto Cc = args(h->lc, false);
+      for (int k = 0; k < p.mu; ++k)
+        hipLaunchKernelGGL((k_bottom<V, CL, CI>), dim3(1), dim3(1024), 0, s, F, Cc, p.nu_pre,
+                           p.nu_post, p.nu_coarse, p.mu, int(k == 0), scale);
+    } else {
+      auto C = args(l - 1, true);
+      if (C.R.n())
+        hipLaunchKernelGGL((k_fas_rhs<V, CL, CI>), dim3(stencil_grid<V>(C.R.n_inner)),
+                           dim3(kBlock), 0, s, C);
+      for (int k = 0; k < p.mu; ++k) fas(l - 1);
+    }
     hipLaunchKernelGGL((k_prolong<V, CL, CI>), dim3(stencil_grid<V>(A.R.n())), dim3(kBlock),
                        0, s,
                        A);

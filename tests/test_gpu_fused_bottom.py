@@ -1,0 +1,56 @@
+"""The bottom of the cycle in one kernel (k_bottom: the FAS step of level
+lc + 1 with the coarsest solves) against the separate kernels it replaces:
+the same preconditioner output, V- and W-cycles, both precisions.
+MFMG_FUSE_BOTTOM=0 at hierarchy build selects the separate kernels."""
+
+import os
+
+import numpy as np
+import pytest
+
+import problems
+from gpu_fixtures import Case, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def case():
+    """Sphere band, leaf levels 4..6: level 4 holds leaves and inner cells."""
+    return Case(2, problems.config_spec(2, 4, 6))
+
+
+def _hierarchy(case, fused, **kw):
+    old = os.environ.get("MFMG_FUSE_BOTTOM")
+    os.environ["MFMG_FUSE_BOTTOM"] = "1" if fused else "0"
+    try:
+        return case.gpu_hierarchy(**kw)
+    finally:
+        if old is None:
+            del os.environ["MFMG_FUSE_BOTTOM"]
+        else:
+            os.environ["MFMG_FUSE_BOTTOM"] = old
+
+
+def test_case_takes_the_fused_path(case):
+    """This case uses k_bottom: the coarsest level is 3 (8 bricks), level 4
+    lies below the finest level 6 and is at most its 4^3 bricks, and no leaf
+    is coarser than level 4, so no level-4 cell has a T-junction."""
+    assert case.T.lmin == 4 and case.T.level.max() == 6
+    assert min(3, case.T.lmin) == 3
+
+
+@pytest.mark.parametrize("precision,mu", [(0, 1), (0, 2), (1, 1), (1, 2)])
+def test_fused_bottom_matches_separate_kernels(case, precision, mu):
+    from paper_2604_18886_amd import mfmg
+    rng = np.random.default_rng(91)
+    r = np.where(case.disc.active, rng.uniform(-1, 1, case.T.n), 0.0)
+    z = []
+    for fused in (True, False):
+        h = _hierarchy(case, fused, precision=precision, mu=mu)
+        z.append(mfmg.apply_precond(h, case.device(r)).cpu().numpy())
+    err = rel(z[0], z[1])
+    print(f"  precision={precision} mu={mu}: fused vs separate {err:.2e}", flush=True)
+    # the same values and sums; only the contraction of a product into a
+    # fused multiply-add may differ between the kernels
+    assert err <= (1e-13 if precision == 0 else 1e-5)
