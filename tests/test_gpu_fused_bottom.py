@@ -54,3 +54,35 @@ def test_fused_bottom_matches_separate_kernels(case, precision, mu):
     # the same values and sums; only the contraction of a product into a
     # fused multiply-add may differ between the kernels
     assert err <= (1e-13 if precision == 0 else 1e-5)
+
+
+@pytest.mark.parametrize("params", [
+    dict(nu_pre=0, nu_post=1, nu_coarse=0, mu=3),
+    dict(nu_pre=1, nu_post=0, nu_coarse=3, mu=1),
+    dict(nu_pre=3, nu_post=2, nu_coarse=1, mu=4),
+])
+def test_fused_bottom_parameter_corners(case, params):
+    """No pre- or post-smoothing, no coarsest sweeps, odd sweep counts and
+    up to four coarse visits: still the separate kernels' output."""
+    from paper_2604_18886_amd import mfmg
+    rng = np.random.default_rng(92)
+    r = np.where(case.disc.active, rng.uniform(-1, 1, case.T.n), 0.0)
+    z = []
+    for fused in (True, False):
+        h = _hierarchy(case, fused, precision=0, **params)
+        z.append(mfmg.apply_precond(h, case.device(r)).cpu().numpy())
+    assert np.abs(z[0]).max() > 0.0
+    assert rel(z[0], z[1]) <= 1e-13
+
+
+def test_fused_bottom_uniform_grid_with_graded_levels():
+    """Uniform 32^3 grid (every level complete): level 4 all inner cells."""
+    from paper_2604_18886_amd import mfmg
+    c = Case(1, problems.config_spec(1))
+    rng = np.random.default_rng(93)
+    r = np.where(c.disc.active, rng.uniform(-1, 1, c.T.n), 0.0)
+    z = []
+    for fused in (True, False):
+        h = _hierarchy(c, fused, precision=1, mu=2)
+        z.append(mfmg.apply_precond(h, c.device(r)).cpu().numpy())
+    assert rel(z[0], z[1]) <= 1e-5
