@@ -157,7 +157,7 @@ struct Scalars {
   int done;      // 1: stop iterating (converged or failed)
   int status;    // 0 running/converged, -5 breakdown
   int iters;
-  int pad;
+  int xpend;     // 1: x still lacks alpha p of the last residual update
 };
 
 }  // namespace mfmg

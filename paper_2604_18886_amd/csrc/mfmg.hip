@@ -1548,7 +1548,7 @@ struct Krylov {
                        0.0);
   }
   void pupdate(const V *z, int first) const {
-    hipLaunchKernelGGL(k_pcg_p<V>, dim3(GA), dim3(kBlock), 0, s, P, z, h->pd.p, first);
+    hipLaunchKernelGGL(k_pcg_p<V>, dim3(GA), dim3(kBlock), 0, s, P, z, h->pd.p, h->x.p, first);
   }
   void Ap(bool trans) const {
     if (trans)
@@ -1563,12 +1563,18 @@ struct Krylov {
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, P, int64_t(trans ? GB : GA),
                        int(kFinAlpha), 0, 0.0);
   }
-  void update(double *x, double *r, V *r_low, int defer) const {
-    hipLaunchKernelGGL(k_pcg_update<V>, dim3(G), dim3(kBlock), 0, s, P, x, r, r_low,
-                       (const double *)h->pd.p, (const double *)h->Ap.p, defer, n2);
+  void update(double *r, V *r_low, int defer) const {
+    hipLaunchKernelGGL(k_pcg_update<V>, dim3(G), dim3(kBlock), 0, s, P, r, r_low,
+                       (const double *)h->Ap.p, defer, n2);
     if (!defer)
       hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, P, int64_t(G), int(kFinUpdate),
                          0, 0.0);
+  }
+  // after the loop: the iterate's last step, if the solve stopped between a
+  // residual update and the k_pcg_p that takes it
+  void finish_x() const {
+    hipLaunchKernelGGL(k_pcg_x, dim3(G), dim3(kBlock), 0, s, P, h->x.p,
+                       (const double *)h->pd.p);
   }
 };
 
@@ -1579,7 +1585,7 @@ static void iteration_body(mfmg_hierarchy *h, double *r, V *r_low, V *z, bool nu
   Reduce R(h, s);
   Krylov<V> K(h, s);
   K.Ap(false);
-  K.update(h->x.p, r, r_low, int(null_space));
+  K.update(r, r_low, int(null_space));
   if (null_space) R.shift_mean<V>(r, r_low, std::max(1.0, h->n_active), 1, 0.0);
   run_cycle(h, s, &h->S.p->done);
   K.rz(r, z, 0);
@@ -1670,6 +1676,7 @@ static void pcg_iterate(mfmg_hierarchy *h, const double *rhs, double *r, V *r_lo
       if (__atomic_load_n(h->host_done, __ATOMIC_ACQUIRE)) break;
     }
   }
+  K.finish_x();
   // zero-mean solution, then the true residual shifted to zero mean
   if (null_space) R.shift_mean<double>(x, (double *)nullptr, na, 3, 0.0);
   hipLaunchKernelGGL(k_full, dim3(G), dim3(kBlock), 0, s, P, (const double *)x, h->Xf.p, 0);
@@ -1769,7 +1776,7 @@ static void pcg_adjoint_iterate(mfmg_hierarchy *h, const double *g, V *z,
   K.pupdate(z, 1);
   for (int it = 0; it < sp->max_iter; ++it) {
     K.Ap(true);
-    K.update(x, r, (V *)nullptr, int(null_space));
+    K.update(r, (V *)nullptr, int(null_space));
     if (null_space) R.shift_mean<V>(r, (V *)nullptr, na, 1, sp->rtol);
     run_cycle_T(h, r, s, done);
     K.rz(r, z, 0);
@@ -1782,6 +1789,7 @@ static void pcg_adjoint_iterate(mfmg_hierarchy *h, const double *g, V *z,
       if (__atomic_load_n(h->host_done, __ATOMIC_ACQUIRE)) break;
     }
   }
+  K.finish_x();
   if (null_space) R.shift_mean<double>(x, (double *)nullptr, na, 3, 0.0);
   // true residual ||g - A^T lambda||
   hipLaunchKernelGGL(k_full, dim3(G), dim3(kBlock), 0, s, P, (const double *)x, h->Xf.p, 0);

@@ -215,18 +215,29 @@ __global__ void __launch_bounds__(kBlock) k_pcg_rz(PcgArgs P, const double *r, c
 // p = z + beta p (p = z on the first call) over the leaf bricks, and for
 // bricks with a T-face the mean of each active sibling group written to the
 // parent's slot of the full-size p: the value the forward composite operator
-// reads for an inner neighbour.
+// reads for an inner neighbour.  After the first call it also takes the
+// iterate's step x += alpha p of the residual update before (Algorithm 1's
+// x update, moved here because this kernel reads p anyway); k_pcg_x adds it
+// when the solve stopped before this kernel ran.
 template <class V>
-__global__ void __launch_bounds__(kBlock) k_pcg_p(PcgArgs P, const V *z, double *p, int first) {
+__global__ void __launch_bounds__(kBlock) k_pcg_p(PcgArgs P, const V *z, double *p, double *x,
+                                                  int first) {
   if (P.S->done) return;
   double beta = first ? 0.0 : P.S->beta;
+  double alpha = P.S->alpha;
   uint32_t m = threadIdx.x & (kWave - 1);
   const __amdgpu_buffer_rsrc_t zr = make_rsrc(z, uint64_t(P.T.nlb) * 64 * sizeof(V));
   const __amdgpu_buffer_rsrc_t pr = make_rsrc(p, uint64_t(P.T.nb) * 64 * sizeof(double));
+  const __amdgpu_buffer_rsrc_t xr = make_rsrc(x, uint64_t(P.T.nlb) * 64 * sizeof(double));
   const WaveLoop W = wave_loop(P.T.nlb);
+  if (!first && blockIdx.x == 0 && threadIdx.x == 0) P.S->xpend = 0;
   for (uint32_t b = W.first; b < W.end; b += W.step) {
     double v = double(bload<V>(zr, m, b * 64u));
-    if (!first) v += beta * bload<double>(pr, m, b * 64u);
+    if (!first) {
+      double po = bload<double>(pr, m, b * 64u);
+      bstore<double>(xr, m, b * 64u, bload<double>(xr, m, b * 64u) + alpha * po);
+      v += beta * po;
+    }
     bstore<double>(pr, m, b * 64u, v);
     const BrickMeta M = load_meta(P.T.meta, b);
     if (M.flags & kFlagT) average_up(p, M, int(m), v);
@@ -288,6 +299,7 @@ enum FinishOp : int {
 
 __device__ __forceinline__ void finish_iteration(const PcgArgs &P, double tot) {
   Scalars *S = P.S;
+  S->xpend = 1;  // the residual update of this iteration is done
   S->rr = tot;
   S->iters += 1;
   P.hist[S->iters] = S->rr0 > 0.0 ? sqrt(tot / S->rr0) : 0.0;
@@ -305,6 +317,7 @@ __device__ __forceinline__ void finish_initial(const PcgArgs &P, double tot, dou
   S->rr = tot;
   S->tol2 = rtol * rtol * tot;
   S->iters = 0;
+  S->xpend = 0;
   S->status = 0;
   S->done = (tot == 0.0) || !(tot < INFINITY);
   if (!(tot < INFINITY)) S->status = -5;
@@ -380,27 +393,22 @@ __global__ void __launch_bounds__(1024) k_finish(PcgArgs P, int64_t n, int op, i
                                       __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// x += alpha p, r -= alpha Ap, ||r||^2 and the stop test
+// r -= alpha Ap, ||r||^2 and the stop test (the iterate's x += alpha p is
+// taken by the next k_pcg_p, or by k_pcg_x after the loop)
 template <class V>
-__global__ void __launch_bounds__(kBlock) k_pcg_update(PcgArgs P, double *x, double *r,
-                                                       V *r_low, const double *p,
+__global__ void __launch_bounds__(kBlock) k_pcg_update(PcgArgs P, double *r, V *r_low,
                                                        const double *Ap, int defer,
                                                        int64_t n2) {
   if (P.S->done) return;
   double alpha = P.S->alpha;
   double part = 0.0;
-  double2 *x2 = reinterpret_cast<double2 *>(x);
   double2 *r2 = reinterpret_cast<double2 *>(r);
-  const double2 *p2 = reinterpret_cast<const double2 *>(p);
   const double2 *a2 = reinterpret_cast<const double2 *>(Ap);
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n2;
        i += int64_t(gridDim.x) * blockDim.x) {
-    double2 xv = x2[i], rv = r2[i], pv = p2[i], av = a2[i];
-    xv.x += alpha * pv.x;
-    xv.y += alpha * pv.y;
+    double2 rv = r2[i], av = a2[i];
     rv.x -= alpha * av.x;
     rv.y -= alpha * av.y;
-    x2[i] = xv;
     r2[i] = rv;
     if (r_low) {
       r_low[2 * i] = V(rv.x);
@@ -410,6 +418,14 @@ __global__ void __launch_bounds__(kBlock) k_pcg_update(PcgArgs P, double *x, dou
   }
   if (defer) return;  // the null-space shift completes this step
   block_partial(part, P.partials);
+}
+
+// x += alpha p when the solve stopped after a residual update and before
+// the k_pcg_p that would have taken the iterate's step.
+__global__ void __launch_bounds__(kBlock) k_pcg_x(PcgArgs P, double *x, const double *p) {
+  if (!P.S->xpend) return;
+  double alpha = P.S->alpha;
+  LEAF_LOOP(P) { x[b * 64u + m] += alpha * p[b * 64u + m]; }
 }
 
 // X (full size, device order) from a leaf vector x; canonical = 1 when x is
