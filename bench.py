@@ -403,11 +403,13 @@ def main():
         "fp64": {"value": out["fp64"]["mcells_per_s"], "ms_per_step": out["fp64"]["ms_per_solve"],
                  "iters": out["fp64"]["iters"], "rel_resid_true": out["fp64"]["rel_resid_true"],
                  "vcycle_gbs": out["fp64"]["cycle_gbs"], "vcycle_ms": out["fp64"]["cycle_ms"],
+                 "vcycle_frac_of_peak": out["fp64"]["cycle_gbs"] / HBM_PEAK_GBS,
                  "adjoint_ms": out["fp64"]["adjoint_ms"],
                  "adjoint_iters": out["fp64"]["adjoint_iters"]},
         "mixed": {"iters": head["iters"], "rel_resid_true": head["rel_resid_true"],
                   "rel_l2_diff_vs_fp64": mixed_vs_fp64,
                   "vcycle_gbs": head["cycle_gbs"], "vcycle_ms": head["cycle_ms"],
+                  "vcycle_frac_of_peak": head["cycle_gbs"] / HBM_PEAK_GBS,
                   "adjoint_ms": head["adjoint_ms"], "adjoint_iters": head["adjoint_iters"],
                   "wcycle_ms_per_solve": dt_w * 1e3, "wcycle_iters": stw["iters"]},
         "rebuild": rebuild,
