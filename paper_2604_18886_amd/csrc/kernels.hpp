@@ -957,7 +957,7 @@ __global__ void __launch_bounds__(1024) k_coarsest(LevelArgs<V, CL, CI> A, int n
 // right-hand side (a W-cycle's second visit: it is already in B).
 constexpr int kBottomCoarse = 1024 / kWave;
 
-// Six local neighbour indices in [-1, 62] packed as bytes (-1: wall).
+// Six local neighbour indices in [-1, 63] packed as bytes (-1: wall).
 __device__ __forceinline__ uint64_t pack_nbr(const BrickMeta &M, const Range &R, uint32_t nlb) {
   uint64_t v = 0;
 #pragma unroll
