@@ -234,9 +234,10 @@ def main():
     if args.summarize_pmc:
         spec = __import__("problems").config_spec(args.workload)
         rec = summarize_pmc(*args.summarize_pmc, spec["max_level"])
-        path = os.path.join(ROOT, "profiles", "traffic_smooth_large_workload.json")
-        with open(path, "w") as fh:
-            json.dump({"mixed": rec}, fh, indent=1)
+        if args.workload == 4:  # the benchmark's workload: the record bench.py reads
+            path = os.path.join(ROOT, "profiles", "traffic_smooth_large_workload.json")
+            with open(path, "w") as fh:
+                json.dump({"mixed": rec}, fh, indent=1)
         print(json.dumps(rec))
         return
     if args.gpus != 1:

@@ -295,7 +295,7 @@ def rhs_manufactured(cfg, leaf_level, leaf_ijk, face_owner=None,
                                    np.asarray(face_ijk).reshape(-1, 3)[dirich],
                                    face_dir[dirich])
             fc = corners.mean(axis=0)
-            hw = np.ldexp(1.0, -np.asarray(face_level)[dirich])
+            hw = np.ldexp(1.0, -np.asarray(face_level, dtype=np.int64)[dirich])
             kw = np.asarray(face_beta_)[dirich] * hw * hw / (theta * hw)
             np.add.at(rhs, np.asarray(face_owner)[dirich],
                       kw * p(fc[:, 0], fc[:, 1], fc[:, 2]))
