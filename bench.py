@@ -229,6 +229,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-pass", action="store_true",
                     help="only the finest mixed half-sweep and a plain copy (counter runs)")
+    ap.add_argument("--traffic-fp64", action="store_true",
+                    help="with --traffic-pass: the FP64 hierarchy's half-sweep instead")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     args = ap.parse_args()
     if args.summarize_pmc:
@@ -280,7 +282,7 @@ def main():
     act = act_d.cpu().numpy()
     L = spec["max_level"]
     if args.traffic_pass:
-        h = mfmg.build_hierarchy(co, precision=mfmg.MIXED)
+        h = mfmg.build_hierarchy(co, precision=mfmg.FP64 if args.traffic_fp64 else mfmg.MIXED)
         ms, by = mfmg.profile(h, mfmg.PROFILE_SMOOTH, L, reps=TRAFFIC_REPS)
         src = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
