@@ -15,8 +15,8 @@ hierarchy are built beforehand.
 Counter passes for the HBM traffic of the finest half-sweep (each under its
 own `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` run):
 
-    python bench.py --traffic-pass          # smoother launches + a plain copy
-    python bench.py --summarize-pmc FETCH.csv WRITE.csv
+    python bench.py --traffic-pass [--traffic-fp64]   # half-sweeps + a plain copy
+    python bench.py --summarize-pmc FETCH.csv WRITE.csv  # mixed or fp64 record
 
 Prints one JSON line.  `value` is the mixed-precision solve rate (FP32
 cycle with FP16 inner coefficients inside FP64 PCG) in million active leaf
@@ -70,11 +70,21 @@ COPY_BYTES = 1 << 30      # plain copy used to scale the counters
 TRAFFIC_REPS = 4
 
 
+def smooth_precision(kernel_name):
+    """Hierarchy a half-sweep dispatch belongs to, from its kernel name:
+    FP32 values (the mixed cycle) or FP64 values."""
+    if "k_smooth<float" in kernel_name:
+        return "mixed"
+    if "k_smooth<double" in kernel_name:
+        return "fp64"
+    return None
+
+
 def summarize_pmc(fetch_csv, write_csv, level):
-    """HBM bytes per launch of the finest mixed half-sweep from two rocprofv3
-    counter_collection.csv files (FETCH_SIZE, WRITE_SIZE in KiB per dispatch),
-    each scaled by what the same counter reads for a plain copy of
-    COPY_BYTES bytes."""
+    """HBM bytes per launch of the finest half-sweep (mixed or FP64, from the
+    kernel name) from two rocprofv3 counter_collection.csv files (FETCH_SIZE,
+    WRITE_SIZE in KiB per dispatch), each scaled by what the same counter
+    reads for a plain copy of COPY_BYTES bytes.  Returns (precision, record)."""
     import csv
 
     def dispatches(path, counter):
@@ -91,9 +101,11 @@ def summarize_pmc(fetch_csv, write_csv, level):
         return [(k, n, v) for k, (n, v) in sorted(acc.items())]
 
     out = {}
+    precisions = set()
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         rows = dispatches(path, counter)
         smooth = [v for _, n, v in rows if "k_smooth" in n]
+        precisions |= {smooth_precision(n) for _, n, _ in rows if "k_smooth" in n}
         last = max((d for d, n, _ in rows if "k_smooth" in n), default=None)
         # the TRAFFIC_REPS device copies of COPY_BYTES that follow the
         # half-sweeps (earlier copy dispatches move other, smaller buffers)
@@ -107,13 +119,16 @@ def summarize_pmc(fetch_csv, write_csv, level):
                         "launches": len(smooth), "copy_raw_bytes": sum(copy) / len(copy),
                         "copy_factor": factor,
                         "per_launch_bytes": sum(smooth) / len(smooth) / factor}
+    if len(precisions) != 1 or None in precisions:
+        raise SystemExit("expected the half-sweeps of one hierarchy, found "
+                         f"{sorted(map(str, precisions))}")
     rec = {"source_hash": kernel_source_hash(), "level": level,
            "fetch_bytes_per_launch": out["FETCH_SIZE"]["per_launch_bytes"],
            "write_bytes_per_launch": out["WRITE_SIZE"]["per_launch_bytes"],
            "hbm_bytes_per_launch": (out["FETCH_SIZE"]["per_launch_bytes"]
                                     + out["WRITE_SIZE"]["per_launch_bytes"]),
            "counters": out}
-    return rec
+    return precisions.pop(), rec
 
 
 def cpu_baseline(sample_levels=(6, 9)):
@@ -235,12 +250,17 @@ def main():
     args = ap.parse_args()
     if args.summarize_pmc:
         spec = __import__("problems").config_spec(args.workload)
-        rec = summarize_pmc(*args.summarize_pmc, spec["max_level"])
+        prec, rec = summarize_pmc(*args.summarize_pmc, spec["max_level"])
         if args.workload == 4:  # the benchmark's workload: the record bench.py reads
             path = os.path.join(ROOT, "profiles", "traffic_smooth_large_workload.json")
+            store = {}
+            if os.path.exists(path):
+                with open(path) as fh:
+                    store = json.load(fh)
+            store[prec] = rec
             with open(path, "w") as fh:
-                json.dump({"mixed": rec}, fh, indent=1)
-        print(json.dumps(rec))
+                json.dump(store, fh, indent=1)
+        print(json.dumps({prec: rec}))
         return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): the solver is "
