@@ -427,6 +427,10 @@ def main():
                  "iters": out["fp64"]["iters"], "rel_resid_true": out["fp64"]["rel_resid_true"],
                  "vcycle_gbs": out["fp64"]["cycle_gbs"], "vcycle_ms": out["fp64"]["cycle_ms"],
                  "vcycle_frac_of_peak": out["fp64"]["cycle_gbs"] / HBM_PEAK_GBS,
+                 "smooth_us": out["fp64"]["smooth_ms"] * 1e3,
+                 "smooth_algorithmic_bytes": out["fp64"]["smooth_bytes"],
+                 "smooth_frac_of_peak": out["fp64"]["smooth_gbs"] / HBM_PEAK_GBS,
+                 "smooth_traffic": measured_traffic("fp64", L),
                  "adjoint_ms": out["fp64"]["adjoint_ms"],
                  "adjoint_iters": out["fp64"]["adjoint_iters"]},
         "mixed": {"iters": head["iters"], "rel_resid_true": head["rel_resid_true"],
