@@ -106,3 +106,51 @@ def test_warm_start_is_a_shifted_cold_start():
     # a guess that already meets the tolerance takes no iteration
     _, i0 = K.pcg(d.A, rhs, H.vcycle, 1e-10, 300, active=d.active, x0=xs)
     assert i0["iters"] == 0 and i0["status"] == 0
+
+
+def test_true_residual_restart():
+    """Stop rule (Algorithm 1 with the FP64 true residual): when the
+    recursively updated residual meets rtol but ||b - A x|| does not, the
+    iteration starts again from x with the true residual.  At rtol 1e-15 on
+    a cut-cell octree the recurrence drifts below the true residual; one
+    restart brings the true residual under rtol, and the reported status is
+    then 0 with true <= rtol."""
+    T, d, beta, rhs = config_problem(3, min_level=4, max_level=6)
+    H = hierarchy(d)
+    x, info = K.pcg(d.A, rhs, H.vcycle, 1e-15, 300, active=d.active)
+    assert info["restarts"] >= 1
+    assert info["status"] == 0 and info["true"] <= 1e-15
+    b = np.where(d.active, rhs, 0.0)
+    assert np.linalg.norm(np.where(d.active, rhs - d.A @ x, 0.0)) <= 1e-15 * np.linalg.norm(b)
+    # the recurrence stopped below rtol before the restart: the history
+    # jumps up at the restart (the true residual) and falls again
+    h = np.array(info["hist"])
+    assert np.any(h[1:] > h[:-1])
+
+
+def test_converged_status_means_true_residual_meets_rtol():
+    """Across the families (uniform Dirichlet, adaptive, cut cells with a
+    Dirichlet top, all-Neumann null space, the transposed system) a status
+    of 0 implies a true residual at or below rtol; a tolerance below the
+    rounding floor ends as not converged, before max_iter (a restart that
+    does not lower the true residual stops the solve)."""
+    cases = []
+    d = disc_for(O.Octree(problems.uniform_spec(4)), seed=21)
+    cases.append((d.A, np.random.default_rng(22).uniform(-1, 1, d.tree.n), hierarchy(d).vcycle,
+                  None, False))
+    d = disc_for(half_tree(3), seed=23)
+    cases.append((d.A, np.random.default_rng(24).uniform(-1, 1, d.tree.n), hierarchy(d).vcycle,
+                  None, False))
+    T, dc, beta, rhs = config_problem(3, min_level=4, max_level=6)
+    Hc = hierarchy(dc)
+    cases.append((dc.A, rhs, Hc.vcycle, dc.active, False))
+    cases.append((dc.A.T.tocsr(), rhs, Hc.vcycle_T, dc.active, False))
+    dn = disc_for(half_tree(3), bc=(D.NEUMANN,) * 6, seed=25)
+    bn = np.random.default_rng(26).uniform(-1, 1, dn.tree.n)
+    cases.append((dn.A, bn - bn.mean(), hierarchy(dn).vcycle, None, True))
+    for A, b, M, act, ns in cases:
+        for rtol in (1e-8, 1e-12, 1e-14):
+            _, info = K.pcg(A, b, M, rtol, 300, active=act, null_space=ns)
+            assert info["status"] == 0 and info["true"] <= rtol, (rtol, info["true"])
+        _, info = K.pcg(A, b, M, 1e-19, 300, active=act, null_space=ns)
+        assert info["status"] == 1 and info["true"] > 1e-19 and info["iters"] < 300
