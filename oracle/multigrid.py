@@ -30,6 +30,13 @@ Readings (the paper is silent or ambiguous)
   * Algorithm 3 is applied as printed; its off-diagonal branch needs no
     activity guard here because a face with non-zero coefficient never
     touches an inactive cell (asserted by the discretisation).
+  * Mixed-precision storage (``stored_precision``): the cycle's arithmetic
+    is unchanged (FP64 here); only its coefficients are replaced by the
+    values a mixed-precision store keeps -- leaf cells in FP32, inner cells
+    as FP16 copies of c/h_l (through FP32, round to nearest even; non-zero
+    values below FP16's normal range raised to 2^-14) -- and the diagonal
+    of every cell by the sum of the six face coefficients it then sees, so
+    each row of a level operator stays conservative.
   * The adjoint solve uses the exact transpose M^T of the cycle M (the
     operator is non-symmetric at T-junctions, so M is not symmetric; PCG on
     A^T needs an approximation of A^-T).  M^T is the cycle's linear steps
@@ -38,6 +45,8 @@ Readings (the paper is silent or ambiguous)
     adjoint of b) accumulates the solution.
 """
 
+import copy
+
 import numpy as np
 import scipy.sparse as sp
 
@@ -45,6 +54,22 @@ from .discretize import DIRV, COARSE as D_COARSE
 from .octree import cell_key
 
 WALL, SAME, COARSE = 0, 1, 2
+
+
+def f32(x):
+    """FP64 -> FP32 (round to nearest even) -> FP64."""
+    return np.asarray(x, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+def stored_value(k, leaf, l):
+    """Coefficients of level-l cells as a mixed-precision store keeps them:
+    FP32 on leaf cells; on inner cells k = h_l * FP16(FP32(k / h_l)), a
+    non-zero value below FP16's normal range (2^-14) raised to 2^-14."""
+    k = np.asarray(k, dtype=np.float64)
+    q = (k * 2.0 ** l).astype(np.float32).astype(np.float16).astype(np.float64)
+    tiny = (k != 0.0) & (np.abs(q) < 2.0 ** -14)
+    q = np.where(tiny, np.copysign(2.0 ** -14, k), q)
+    return np.where(leaf, f32(k), q * 2.0 ** -l)
 
 
 class Level:
@@ -178,6 +203,50 @@ class Hierarchy:
         Lv.kx[inner] = cx
         Lv.ky[inner] = cy
         Lv.kz[inner] = cz
+
+    # ------------------------------------------------- stored precision
+    def stored_precision(self):
+        """A copy of the hierarchy whose level coefficients are those of a
+        mixed-precision store (FP32 leaf cells, FP16 c/h_l inner cells; see
+        the module readings), with the operators rebuilt from them.  The
+        input transformation of the mixed-precision cycle: its FP64 cycle
+        is the mixed cycle's arithmetic done exactly."""
+        H = copy.copy(self)
+        H.levels = {}
+        for l, Lv0 in self.levels.items():
+            Lv = copy.copy(Lv0)
+            own = [Lv0.kx, Lv0.ky, Lv0.kz]
+            rown = [stored_value(k, Lv0.leaf, l) for k in own]
+            plus64 = [self.face_coef(l, 2 * a + 1) for a in range(3)]
+            rplus = []
+            for a in range(3):
+                kind = Lv0.nkind[:, 2 * a + 1]
+                idx = Lv0.nidx[:, 2 * a + 1]
+                v = np.zeros(Lv0.n)
+                same = kind == SAME
+                v[same] = rown[a][idx[same]]
+                co = kind == COARSE
+                v[co] = f32(Lv0.kplus[co, a])
+                rplus.append(v)
+            # the wall part of the FP64 diagonal (its plus-wall faces), in
+            # FP32 on the first plus wall of the cell
+            wall = np.stack([Lv0.nkind[:, 2 * a + 1] == WALL for a in range(3)], axis=1)
+            wpart = Lv0.c - (own[0] + own[1] + own[2]) - (plus64[0] + plus64[1] + plus64[2])
+            first = np.argmax(wall, axis=1)
+            anyw = wall.any(axis=1)
+            for a in range(3):
+                m = anyw & (first == a)
+                rplus[a][m] = f32(wpart[m])
+            Lv.kx, Lv.ky, Lv.kz = rown
+            Lv.kplus = np.stack([np.where(Lv0.nkind[:, 2 * a + 1] == COARSE, rplus[a],
+                                          Lv0.kplus[:, a]) for a in range(3)], axis=1)
+            Lv.kplus[Lv0.leaf] = f32(Lv.kplus[Lv0.leaf])
+            c = ((rown[0] + rplus[0]) + (rown[1] + rplus[1])) + (rown[2] + rplus[2])
+            Lv.c = np.where(Lv0.active, c, 0.0)
+            H.levels[l] = Lv
+        for l in range(H.L, H.lc - 1, -1):
+            H._operators(l)
+        return H
 
     # ---------------------------------------------------------- operators
     def _neighbours(self, l):
