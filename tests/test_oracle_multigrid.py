@@ -200,3 +200,64 @@ def test_cycle_transpose_is_exact_adjoint(maker):
         Mm = np.stack([H.vcycle(e) for e in np.eye(n)[:200]], axis=1)
         Mt = np.stack([H.vcycle_T(e) for e in np.eye(n)], axis=1)
         assert np.allclose(Mt[:200, :].T, Mm, rtol=0, atol=1e-13 * np.abs(Mm).max())
+
+
+def _level_values(H, u):
+    """Level vectors of a leaf vector: leaves hold their own value, inner
+    cells the mean of their active children (recursively), i.e. the value
+    the composite operator uses for an inner neighbour (Section 3.1)."""
+    vals = {}
+    for l in range(H.L, H.lc - 1, -1):
+        Lv = H.levels[l]
+        v = np.zeros(Lv.n)
+        v[Lv.leaf] = u[Lv.leaf_idx[Lv.leaf]]
+        if l < H.L:
+            v[~Lv.leaf] = (H.levels[l + 1].Avg @ vals[l + 1])[~Lv.leaf]
+        vals[l] = v
+    return vals
+
+
+@pytest.mark.parametrize("maker", ["three", "cut", "half_y"])
+def test_level_tjunction_rows_equal_composite_rows(maker):
+    """Pin of the level operators' leaf rows, T-junction coupling B^l
+    included (Section 3.1, Eqs. (7)-(10); Algorithm 3 coarse coefficients):
+    with inner cells holding the mean of their active children, the row
+    (A^l u_l + B^l u_{l-1})_i of every active leaf i of every level is the
+    composite operator's row (A u)_i, which is assembled independently and
+    pinned by conservation, the direct solves and second-order convergence.
+    A wrong ghost weight (the 1/2 on u_J, the 1/(2 n) on the siblings) or a
+    coarse coefficient other than the sum of the sub-faces over 2 fails it."""
+    from oracle_fixtures import config_problem, three_level_nodes
+    if maker == "three":
+        T = O.Octree({"min_level": 3, "max_level": 5, "node_size": 4, "prims": []},
+                     three_level_nodes(3))
+        d = disc_for(T, seed=41)
+    elif maker == "half_y":
+        d = disc_for(half_tree(3, axis=1), seed=42)
+    else:
+        _, d, _, _ = config_problem(3, min_level=4, max_level=6)
+    H = hierarchy(d)
+    rng = np.random.default_rng(43)
+    u = np.where(d.active, rng.uniform(-1.0, 1.0, d.tree.n), 0.0)
+    Au = d.A @ u
+    vals = _level_values(H, u)
+    n_t = 0
+    for l in range(H.L, H.lc - 1, -1):
+        Lv = H.levels[l]
+        y = Lv.A @ vals[l]
+        if Lv.B is not None:
+            y = y + Lv.B @ vals[l - 1]
+        rows = np.nonzero(Lv.leaf & Lv.active)[0]
+        ref = Au[Lv.leaf_idx[rows]]
+        assert np.allclose(y[rows], ref, rtol=0.0, atol=1e-13 * max(np.abs(Au).max(), 1e-300))
+        n_t += int((Lv.nkind[rows] == 2).any(axis=1).sum())
+    assert n_t > 0
+    # the check is sensitive: a ghost weight of 1/4 instead of 1/2 on u_J
+    # changes the T rows
+    L = H.L
+    Lv = H.levels[L]
+    if Lv.B is not None and Lv.B.nnz:
+        y_bad = Lv.A @ vals[L] + 0.5 * (Lv.B @ vals[L - 1])
+        rows = np.nonzero(Lv.leaf & Lv.active)[0]
+        assert not np.allclose(y_bad[rows], Au[Lv.leaf_idx[rows]], rtol=0.0,
+                               atol=1e-13 * np.abs(Au).max())
