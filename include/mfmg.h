@@ -180,7 +180,11 @@ void mfmg_destroy_coeffs(mfmg_coeffs *coeffs);
  * come from Algorithm 3 (Section 2.5) with restriction scale alpha.
  * precision MFMG_FP64: the cycle runs in FP64.  MFMG_MIXED: the cycle runs
  * in FP32 with FP32 leaf coefficients and FP16 inner coefficients stored as
- * c / h_l; the outer PCG, its dot products and the true residual stay FP64.
+ * c / h_l (round to nearest even through FP32; a non-zero value below FP16's
+ * normal range is stored as +-2^-14, so a sliver cut face keeps a positive
+ * coupling and no active cell gets a zero diagonal); the outer PCG, its dot
+ * products and the true residual stay FP64.  Every cycle kernel forms a
+ * cell's diagonal as the sum of the six face coefficients it reads.
  */
 enum { MFMG_FP64 = 0, MFMG_MIXED = 1 };
 
@@ -222,7 +226,8 @@ void mfmg_destroy_hierarchy(mfmg_hierarchy *h);
 
 /* ------------------------------------------------------------------- solve */
 typedef struct {
-  double rtol;    /* stop when ||r_k||_2 <= rtol ||r_0||_2 (1e-10)           */
+  double rtol;    /* stop when ||r_k||_2 <= rtol ||r_0||_2 (1e-10); see the  */
+                  /* true-residual rule at mfmg_pcg_solve                     */
   int max_iter;   /* iteration cap (200)                                      */
   int null_space; /* -1 auto (on iff no Dirichlet wall), 0 off, 1 on: shift */
                   /* the residual to zero mean over active cells (Sec. 2.2)  */
@@ -245,17 +250,28 @@ typedef struct {
  * in canonical order; entries of inactive leaves are ignored on input and
  * set to 0 on output.  hist (host, may be NULL) receives max_iter + 1
  * relative residuals (the first iters + 1 are meaningful).
- * Returns OK, NOT_CONVERGED (p holds the last iterate), BREAKDOWN,
- * INCOMPATIBLE_RHS (null_space = 0 on a problem without Dirichlet faces and
- * |sum of rhs| > 1e-10 sum of |rhs| over the active cells: A is singular on
- * the constants and the system has no solution; nothing is solved), or an
- * error. */
+ * Stop rule (Algorithm 1's residual test, read with a true-residual check):
+ * the iteration stops when the recursively updated residual meets rtol;
+ * then the FP64 true residual ||rhs - A p|| is formed, and while it exceeds
+ * rtol ||r_0|| and fewer than max_iter iterations were taken, the iteration
+ * starts again from p with r = rhs - A p (same tolerance, the iteration
+ * budget shared).  A restart that does not lower the true residual ends the
+ * solve.  OK therefore means both residuals meet rtol.  In MFMG_MIXED the
+ * cycle reads the residual multiplied by a power of two that brings its
+ * mean square to [1, 4) (undone exactly in FP64), so the solve does not
+ * depend on the scale of rhs within FP64's range.
+ * Returns OK, NOT_CONVERGED (p holds the last iterate; the recursive or the
+ * true residual is above rtol), BREAKDOWN, INCOMPATIBLE_RHS (null_space = 0
+ * on a problem without Dirichlet faces and |sum of rhs| > 1e-10 sum of |rhs|
+ * over the active cells: A is singular on the constants and the system has
+ * no solution; nothing is solved), or an error. */
 mfmg_status mfmg_pcg_solve(mfmg_hierarchy *h, const double *rhs, double *p,
                            const mfmg_solve_params *params, void *stream,
                            mfmg_solve_stats *stats, double *hist);
 
 /* Adjoint of the solve: lambda with A^T lambda = dL_dp, preconditioned by
- * the exact transpose of the cycle, then per face
+ * the exact transpose of the cycle (same stop rule and residual scaling as
+ * mfmg_pcg_solve), then per face
  *   dL/dbeta_f = -lambda^T (dA/dbeta_f) p
  * (0 at Neumann walls and where a side of the face is inactive).
  * p, dL_dp, lambda: device, n_leaves; dL_dbeta: device, n_faces.
@@ -296,6 +312,7 @@ mfmg_status mfmg_project_velocity(mfmg_hierarchy *h, const double *face_beta,
  * leaves, V_i = h_i^3.  Returns after the stream has drained. */
 mfmg_status mfmg_divergence_rms(mfmg_hierarchy *h, const double *div, double *rms,
                                 void *stream);
+
 
 /* ------------------------------------------------ component entry points
  * For parity tests of single steps.  Device vectors of n_leaves doubles. */

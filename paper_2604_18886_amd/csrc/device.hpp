@@ -154,6 +154,7 @@ struct Scalars {
   double sum;    // scratch: sum for the null-space mean
   double cnt;    // scratch: active count
   double tr;     // ||rhs - A x||^2 of the true residual
+  double rscale; // power of two the cycle's input (the residual) is scaled by
   int done;      // 1: stop iterating (converged or failed)
   int status;    // 0 running/converged, -5 breakdown
   int iters;

@@ -256,6 +256,18 @@ __global__ void k_convert_leaf(const double *src, float *dst, int64_t n) {
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = float(src[i]);
 }
+// FP16 copy of an inner coefficient scaled to c / h_l (through FP32, round to
+// nearest even).  A non-zero value that would land below FP16's normal range
+// (2^-14) is stored as 2^-14 with its sign: a sliver face keeps a small
+// positive coupling instead of vanishing, so no cell that is active in FP64
+// gets a zero diagonal in the mixed-precision cycle.
+__device__ __forceinline__ __half half_coef(double v) {
+  __half q = __float2half_rn(float(v));
+  if (v != 0.0 && fabsf(__half2float(q)) < 0x1p-14f)
+    q = __float2half_rn(v < 0.0 ? -0x1p-14f : 0x1p-14f);
+  return q;
+}
+
 // FP64 inner coefficients -> FP16 copies of c / h_l
 __global__ void __launch_bounds__(kBlock) k_convert_inner(const double *coef, Topo T,
                                                           __half *dst) {
@@ -265,8 +277,7 @@ __global__ void __launch_bounds__(kBlock) k_convert_inner(const double *coef, To
   if (b >= T.nb) return;
   double inv_h = ldexp(1.0, T.meta[b].level);
   for (int comp = 0; comp < 4; ++comp)
-    dst[i * 256u + comp * 64 + m] =
-        __float2half_rn(float(coef[b * 256u + comp * 64 + m] * inv_h));
+    dst[i * 256u + comp * 64 + m] = half_coef(coef[b * 256u + comp * 64 + m] * inv_h);
 }
 
 // Plus-face coefficients of every brick, for the level kernels: entry
@@ -322,7 +333,7 @@ __global__ void __launch_bounds__(kBlock) k_plus_faces(Topo T, const double *coe
                          (kp[0] + kp[1] + kp[2])
                    : 0.0;
   } else if (half_inner && inner_nbr) {
-    float hv = __half2float(__float2half_rn(float(v * ldexp(1.0, M.level))));
+    float hv = __half2float(half_coef(v * ldexp(1.0, M.level)));
     v = double(hv * ldexpf(1.0f, -M.level));
   }
   pf[b * 48u + e] = CL(v);
@@ -1290,9 +1301,21 @@ __device__ __forceinline__ void sweep_w_brick(const LevelViewT<V, CL, CI, CP> &X
                                               const LaneC<V, CL> &L, uint32_t b, int colour) {
   const BrickMeta M = load_meta(X.c.meta, b);
   bool act = (act_mask(M) >> L.m) & 1ull;
+  // the diagonal the forward half-sweep divides by: the sum of the six face
+  // coefficients the stencil sees (own k on the minus faces, the partner's
+  // or the plus-face table's on the plus faces), summed in the same order
+  V kd[6];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    V kown = own_coef<INNER>(X.c, b, 1 + a, L.m);
+    V kl = V(bload_bytes<CL, CP>(X.c.pf, L.foff[a], b * uint32_t(48 * sizeof(CL))));
+    V ks = shfl(kown, L.p[2 * a + 1]);
+    kd[2 * a] = kown;
+    kd[2 * a + 1] = L.out[2 * a + 1] ? kl : ks;
+  }
+  V c = ((kd[0] + kd[1]) + (kd[2] + kd[3])) + (kd[4] + kd[5]);
   V x = V(0);
-  if (act && L.colour == colour)
-    x = div_by(bload<V>(X.rho, L.m, b * 64u), own_coef<INNER>(X.c, b, 0, L.m));
+  if (act && L.colour == colour) x = div_by(bload<V>(X.rho, L.m, b * 64u), c);
   bstore<V>(X.w, L.m, b * 64u, x);
 }
 
@@ -1515,10 +1538,12 @@ __global__ void k_couple_list(const BrickMeta *meta, uint32_t nlb, const int64_t
   if (b < nlb && (meta[b].flags & kFlagInner)) list[pos[b]] = b;
 }
 
+// dst = V(src * scale): the transposed cycle's input (scale: the power of
+// two of the solve's scalars, or null for 1)
 template <class V>
-__global__ void k_T_load(const double *src, V *dst, int64_t n) {
+__global__ void k_T_load(const double *src, V *dst, int64_t n, const double *scale) {
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = V(src[i]);
+  if (i < n) dst[i] = V(scale ? src[i] * *scale : src[i]);
 }
 
 template <class V>

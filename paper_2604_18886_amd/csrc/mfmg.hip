@@ -1285,14 +1285,16 @@ struct CycleT {
       launch_apply(l, -1, W);
     }
   }
-  // input: an FP64 leaf vector in device order
-  void run(const double *in) const {
+  // input: an FP64 leaf vector in device order, multiplied by *scale on
+  // loading (scale may be null)
+  void run(const double *in, const double *scale) const {
     const DeviceTopology &D = *h->co->dt;
     int64_t nb64 = int64_t(D.nb) * 64, N = int64_t(D.nlb) * 64;
     hipLaunchKernelGGL((k_fill<V>), dim3(grid_elems(nb64, 256)), dim3(256), 0, s, Y, nb64, V(0));
     hipLaunchKernelGGL((k_fill<V>), dim3(grid_elems(nb64 - N, 256)), dim3(256), 0, s, RHO + N,
                        nb64 - N, V(0));
-    hipLaunchKernelGGL((k_T_load<V>), dim3(grid_elems(N, 256)), dim3(256), 0, s, in, RHO, N);
+    hipLaunchKernelGGL((k_T_load<V>), dim3(grid_elems(N, 256)), dim3(256), 0, s, in, RHO, N,
+                       scale);
     fas_T(h->L);
   }
 };
@@ -1339,16 +1341,17 @@ static void ensure_coupling_lists(mfmg_hierarchy *h, hipStream_t s) {
 }
 
 // z = M^T r: r, z FP64 leaf vectors in device order; returns the z buffer
-// (the Y leaf part, of the cycle's value type)
+// (the Y leaf part, of the cycle's value type).  In mixed precision the
+// solve passes its scalars' residual scale (scale), so z is M^T (scale r).
 void run_cycle_T(mfmg_hierarchy *h, const double *r, hipStream_t s,
-                 const int *done = nullptr) {
+                 const int *done = nullptr, const double *scale = nullptr) {
   ensure_coupling_lists(h, s);
   if (h->prm.precision == MFMG_MIXED) {
     alloc_transpose(h, h->T32);
     CycleT<float, float, __half> c{h, h->coef32.p, h->coef16.p, h->tc32.p, h->pf32.p,
                                    h->T32[0].p, h->T32[1].p, h->T32[2].p, h->T32[3].p,
                                    h->T32[4].p, h->T32[5].p, s, done};
-    c.run(r);
+    c.run(r, scale);
   } else {
     alloc_transpose(h, h->T64);
     CycleT<double, double, double> c{h, h->coef64.p,
@@ -1356,7 +1359,7 @@ void run_cycle_T(mfmg_hierarchy *h, const double *r, hipStream_t s,
                                      h->co->tc.p, h->pf64.p, h->T64[0].p, h->T64[1].p,
                                      h->T64[2].p, h->T64[3].p, h->T64[4].p, h->T64[5].p, s,
                                      done};
-    c.run(r);
+    c.run(r, nullptr);
   }
 }
 
@@ -1371,6 +1374,7 @@ PcgArgs pcg_args(mfmg_hierarchy *h) {
   P.partials = h->partials.p;
   P.hist = h->hist.p;
   P.host_done = h->host_done_dev;
+  P.scale_low = h->prm.precision == MFMG_MIXED ? 1 : 0;
   return P;
 }
 
@@ -1632,36 +1636,31 @@ static hipGraphExec_t iteration_graph(mfmg_hierarchy *h, double *r, V *r_low, V 
   return ge;
 }
 
+// The stop test of Algorithm 1 is taken on the recursively updated residual;
+// after it fires the FP64 true residual ||rhs - A x|| is formed.  While that
+// exceeds the tolerance and iterations are left, the iteration starts again
+// from x with r = rhs - A x (tolerance and iteration budget unchanged), so a
+// solve reported as converged meets rtol in its true residual.  A restart that
+// does not lower the true residual ends the solve (not converged).
+// Status of a finished solve from its scalars: breakdown, not converged
+// (recurrence or true residual above the tolerance), or OK.
+static mfmg_status solve_status(const Scalars &S) {
+  if (S.status == -5) return MFMG_ERR_BREAKDOWN;
+  if (S.rr0 > 0.0 && (!(S.rr <= S.tol2) || !(S.tr <= S.tol2))) return MFMG_NOT_CONVERGED;
+  return MFMG_OK;
+}
+
+static bool restart_wanted(const Scalars &S, int max_iter, double prev_tr) {
+  return S.status == 0 && S.rr0 > 0.0 && S.rr <= S.tol2 && S.tr > S.tol2 &&
+         S.iters < max_iter && S.tr < prev_tr;
+}
+
+// Queue up to n iterations of the loop body; returns when the stop flag is
+// seen or n have been queued.
 template <class V>
-static void pcg_iterate(mfmg_hierarchy *h, const double *rhs, double *r, V *r_low, V *z,
-                        const mfmg_solve_params *sp, bool null_space, hipStream_t s,
-                        const double *x0) {
-  PcgArgs P = pcg_args(h);
-  unsigned G = grid_reduce(h->co->dt->nlb);
-  Reduce R(h, s);
-  const int *done = &h->S.p->done;
-  double na = std::max(1.0, h->n_active);
-  double *x = h->x.p;
-  __atomic_store_n(h->host_done, 0, __ATOMIC_RELEASE);  // the stream is idle here
-  R.init<V>(rhs, r, r_low, x, sp->rtol);
-  if (null_space) R.shift_mean<V>(r, r_low, na, 0, sp->rtol);
-  if (x0) {
-    // r = rhs - A x0; the tolerance stays rtol ||rhs|| from the step above
-    hipLaunchKernelGGL(k_full, dim3(G), dim3(kBlock), 0, s, P, x0, h->Xf.p, 1);
-    hipLaunchKernelGGL(k_residual_vec, dim3(level_grid(h->co->dt->nlb)), dim3(kBlock), 0, s,
-                       P, rhs, (const double *)h->Xf.p, r);
-    hipLaunchKernelGGL(k_warm_start<V>, dim3(G), dim3(kBlock), 0, s, P, x0, x,
-                       (const double *)r, r_low);
-    R.finish(G, kFinWarm);
-  }
-  Krylov<V> K(h, s);
-  run_cycle(h, s, done);
-  K.rz(r, z, 1);
-  K.pupdate(z, 1);
-  hipGraphExec_t body = graphs_enabled() && sp->max_iter > 0
-                           ? iteration_graph<V>(h, r, r_low, z, null_space)
-                           : nullptr;
-  for (int it = 0; it < sp->max_iter; ++it) {
+static void run_iterations(mfmg_hierarchy *h, double *r, V *r_low, V *z, bool null_space,
+                           int n, hipGraphExec_t body, hipStream_t s) {
+  for (int it = 0; it < n; ++it) {
     if (body)
       HIP_CHECK(hipGraphLaunch(body, s));
     else
@@ -1676,16 +1675,70 @@ static void pcg_iterate(mfmg_hierarchy *h, const double *rhs, double *r, V *r_lo
       if (__atomic_load_n(h->host_done, __ATOMIC_ACQUIRE)) break;
     }
   }
-  K.finish_x();
-  // zero-mean solution, then the true residual shifted to zero mean
-  if (null_space) R.shift_mean<double>(x, (double *)nullptr, na, 3, 0.0);
-  hipLaunchKernelGGL(k_full, dim3(G), dim3(kBlock), 0, s, P, (const double *)x, h->Xf.p, 0);
-  if (null_space) {
-    hipLaunchKernelGGL(k_residual_vec, dim3(level_grid(h->co->dt->nlb)), dim3(kBlock), 0, s,
-                       P, rhs, (const double *)h->Xf.p, h->Ap.p);
-    R.shift_mean<double>(h->Ap.p, (double *)nullptr, na, 2, 0.0);
-  } else {
-    R.true_resid(rhs, (const double *)h->Xf.p, h->co->dt->nlb);
+}
+
+template <class V>
+static void pcg_iterate(mfmg_hierarchy *h, const double *rhs, double *r, V *r_low, V *z,
+                        const mfmg_solve_params *sp, bool null_space, hipStream_t s,
+                        const double *x0) {
+  PcgArgs P = pcg_args(h);
+  unsigned G = grid_reduce(h->co->dt->nlb);
+  unsigned GL = level_grid(h->co->dt->nlb);
+  Reduce R(h, s);
+  const int *done = &h->S.p->done;
+  double na = std::max(1.0, h->n_active);
+  double *x = h->x.p;
+  __atomic_store_n(h->host_done, 0, __ATOMIC_RELEASE);  // the stream is idle here
+  R.init<V>(rhs, r, (V *)nullptr, x, sp->rtol);
+  if (null_space) R.shift_mean<V>(r, (V *)nullptr, na, 0, sp->rtol);
+  if (x0) {
+    // r = rhs - A x0; the tolerance stays rtol ||rhs|| from the step above
+    hipLaunchKernelGGL(k_full, dim3(G), dim3(kBlock), 0, s, P, x0, h->Xf.p, 1);
+    hipLaunchKernelGGL(k_residual_vec, dim3(GL), dim3(kBlock), 0, s, P, rhs,
+                       (const double *)h->Xf.p, r);
+    hipLaunchKernelGGL(k_warm_start<V>, dim3(G), dim3(kBlock), 0, s, P, x0, x,
+                       (const double *)r, (V *)nullptr);
+    R.finish(G, kFinWarm);
+  }
+  if (r_low) hipLaunchKernelGGL(k_scale_low<V>, dim3(G), dim3(kBlock), 0, s, P, r, r_low);
+  Krylov<V> K(h, s);
+  run_cycle(h, s, done);
+  K.rz(r, z, 1);
+  K.pupdate(z, 1);
+  hipGraphExec_t body = graphs_enabled() && sp->max_iter > 0
+                           ? iteration_graph<V>(h, r, r_low, z, null_space)
+                           : nullptr;
+  double prev_tr = INFINITY;
+  int left = sp->max_iter;
+  for (;;) {
+    run_iterations<V>(h, r, r_low, z, null_space, left, body, s);
+    K.finish_x();
+    // zero-mean solution, then the true residual (shifted to zero mean)
+    if (null_space) R.shift_mean<double>(x, (double *)nullptr, na, 3, 0.0);
+    hipLaunchKernelGGL(k_full, dim3(G), dim3(kBlock), 0, s, P, (const double *)x, h->Xf.p, 0);
+    if (null_space) {
+      hipLaunchKernelGGL(k_residual_vec, dim3(GL), dim3(kBlock), 0, s, P, rhs,
+                         (const double *)h->Xf.p, h->Ap.p);
+      R.shift_mean<double>(h->Ap.p, (double *)nullptr, na, 2, 0.0);
+    } else {
+      R.true_resid(rhs, (const double *)h->Xf.p, h->co->dt->nlb);
+    }
+    HIP_CHECK(hipMemcpyAsync(h->hostS, h->S.p, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    const Scalars S = *h->hostS;
+    if (!restart_wanted(S, sp->max_iter, prev_tr)) break;
+    prev_tr = S.tr;
+    left = sp->max_iter - S.iters;
+    // r = rhs - A x (the null-space form is already in Ap)
+    if (!null_space)
+      hipLaunchKernelGGL(k_residual_vec, dim3(GL), dim3(kBlock), 0, s, P, rhs,
+                         (const double *)h->Xf.p, h->Ap.p);
+    hipLaunchKernelGGL(k_restart, dim3(G), dim3(kBlock), 0, s, P, (const double *)h->Ap.p, r);
+    R.finish(G, kFinRestart);
+    if (r_low) hipLaunchKernelGGL(k_scale_low<V>, dim3(G), dim3(kBlock), 0, s, P, r, r_low);
+    run_cycle(h, s, done);
+    K.rz(r, z, 1);
+    K.pupdate(z, 1);
   }
   HIP_CHECK(hipGetLastError());
 }
@@ -1734,10 +1787,7 @@ extern "C" mfmg_status mfmg_pcg_solve(mfmg_hierarchy *h, const double *rhs, doub
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     const Scalars &S = *h->hostS;
-    if (S.status == -5)
-      st = MFMG_ERR_BREAKDOWN;
-    else if (S.rr0 > 0.0 && !(S.rr <= S.tol2))
-      st = MFMG_NOT_CONVERGED;
+    st = solve_status(S);
     if (stats) {
       stats->iters = S.iters;
       stats->status = st;
@@ -1752,12 +1802,16 @@ extern "C" mfmg_status mfmg_pcg_solve(mfmg_hierarchy *h, const double *rhs, doub
     return hip_fail(e);
   }
   if (st == MFMG_ERR_BREAKDOWN) return fail(st, "PCG breakdown: (r,z) or (p,Ap) not positive");
-  if (st == MFMG_NOT_CONVERGED) g_err = "not converged within max_iter";
+  if (st == MFMG_NOT_CONVERGED)
+    g_err = "not converged: the residual (recursive or true) is above rtol after max_iter "
+            "iterations or at the rounding floor";
   return st;
 }
 
 // Adjoint PCG: A^T lambda = g preconditioned by M^T (Algorithm 1 with the
-// transposed operator and cycle).
+// transposed operator and cycle), with the same restart rule as the forward
+// solve.  On return Xf holds the true residual g - A^T lambda in device
+// order (shifted to zero mean with the null space) and S->tr its norm.
 template <class V>
 static void pcg_adjoint_iterate(mfmg_hierarchy *h, const double *g, V *z,
                                 const mfmg_solve_params *sp, bool null_space, hipStream_t s) {
@@ -1767,34 +1821,54 @@ static void pcg_adjoint_iterate(mfmg_hierarchy *h, const double *g, V *z,
   double na = std::max(1.0, h->n_active);
   double *x = h->x.p, *r = h->rA.p;
   const int *done = &h->S.p->done;
+  const double *scale = &h->S.p->rscale;  // 1 in FP64
   __atomic_store_n(h->host_done, 0, __ATOMIC_RELEASE);  // the stream is idle here
   R.init<V>(g, r, (V *)nullptr, x, sp->rtol);
   if (null_space) R.shift_mean<V>(r, (V *)nullptr, na, 0, sp->rtol);
   Krylov<V> K(h, s);
-  run_cycle_T(h, r, s, done);
+  run_cycle_T(h, r, s, done, scale);
   K.rz(r, z, 1);
   K.pupdate(z, 1);
-  for (int it = 0; it < sp->max_iter; ++it) {
-    K.Ap(true);
-    K.update(r, (V *)nullptr, int(null_space));
-    if (null_space) R.shift_mean<V>(r, (V *)nullptr, na, 1, sp->rtol);
-    run_cycle_T(h, r, s, done);
-    K.rz(r, z, 0);
-    K.pupdate(z, 0);
-    // stop flag of iteration it read after iteration it + 1 is queued (as in
-    // the forward solve); kernels queued after the stop return at once
-    HIP_CHECK(hipEventRecord(h->iter_ev[it & 1], s));
-    if (it > 0) {
-      HIP_CHECK(hipEventSynchronize(h->iter_ev[(it - 1) & 1]));
-      if (__atomic_load_n(h->host_done, __ATOMIC_ACQUIRE)) break;
+  double prev_tr = INFINITY;
+  int left = sp->max_iter;
+  for (;;) {
+    for (int it = 0; it < left; ++it) {
+      K.Ap(true);
+      K.update(r, (V *)nullptr, int(null_space));
+      if (null_space) R.shift_mean<V>(r, (V *)nullptr, na, 1, sp->rtol);
+      run_cycle_T(h, r, s, done, scale);
+      K.rz(r, z, 0);
+      K.pupdate(z, 0);
+      // stop flag of iteration it read after iteration it + 1 is queued (as in
+      // the forward solve); kernels queued after the stop return at once
+      HIP_CHECK(hipEventRecord(h->iter_ev[it & 1], s));
+      if (it > 0) {
+        HIP_CHECK(hipEventSynchronize(h->iter_ev[(it - 1) & 1]));
+        if (__atomic_load_n(h->host_done, __ATOMIC_ACQUIRE)) break;
+      }
     }
+    K.finish_x();
+    if (null_space) R.shift_mean<double>(x, (double *)nullptr, na, 3, 0.0);
+    // true residual g - A^T lambda (into Xf) and its norm
+    hipLaunchKernelGGL(k_full, dim3(G), dim3(kBlock), 0, s, P, (const double *)x, h->Xf.p, 0);
+    hipLaunchKernelGGL(k_applyT, dim3(G), dim3(kBlock), 0, s, P, (const double *)h->Xf.p,
+                       h->Ap.p);
+    hipLaunchKernelGGL(k_resid_T, dim3(G), dim3(kBlock), 0, s, P, g, (const double *)h->Ap.p,
+                       h->Xf.p);
+    R.finish(G, kFinTrue);
+    if (null_space) R.shift_mean<double>(h->Xf.p, (double *)nullptr, na, 2, 0.0);
+    HIP_CHECK(hipMemcpyAsync(h->hostS, h->S.p, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    const Scalars S = *h->hostS;
+    if (!restart_wanted(S, sp->max_iter, prev_tr)) break;
+    prev_tr = S.tr;
+    left = sp->max_iter - S.iters;
+    hipLaunchKernelGGL(k_restart, dim3(G), dim3(kBlock), 0, s, P, (const double *)h->Xf.p, r);
+    R.finish(G, kFinRestart);
+    run_cycle_T(h, r, s, done, scale);
+    K.rz(r, z, 1);
+    K.pupdate(z, 1);
   }
-  K.finish_x();
-  if (null_space) R.shift_mean<double>(x, (double *)nullptr, na, 3, 0.0);
-  // true residual ||g - A^T lambda||
-  hipLaunchKernelGGL(k_full, dim3(G), dim3(kBlock), 0, s, P, (const double *)x, h->Xf.p, 0);
-  hipLaunchKernelGGL(k_applyT, dim3(G), dim3(kBlock), 0, s, P, (const double *)h->Xf.p,
-                     h->Ap.p);
   HIP_CHECK(hipGetLastError());
 }
 
@@ -1840,16 +1914,6 @@ extern "C" mfmg_status mfmg_pcg_solve_adjoint(mfmg_hierarchy *h, const double *p
     unsigned G = grid_for(D.nlb);
     hipLaunchKernelGGL(k_to_canonical<double>, dim3(G), dim3(kBlock), 0, s, P,
                        (const double *)h->x.p, lambda);
-    // true residual of the adjoint system, ||dL/dp - A^T lambda|| (shifted
-    // to zero mean with the null space), on the device
-    {
-      Reduce R(h, s);
-      hipLaunchKernelGGL(k_resid_T, dim3(R.G), dim3(kBlock), 0, s, P, dL_dp,
-                         (const double *)h->Ap.p, h->Xf.p);
-      R.finish(R.G, kFinTrue);
-      if (ns) R.shift_mean<double>(h->Xf.p, (double *)nullptr, std::max(1.0, h->n_active), 2,
-                                   0.0);
-    }
     GradArgs A;
     A.owner = h->f_owner.p;
     A.other = h->f_other.p;
@@ -1872,10 +1936,7 @@ extern "C" mfmg_status mfmg_pcg_solve_adjoint(mfmg_hierarchy *h, const double *p
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     const Scalars &S = *h->hostS;
-    if (S.status == -5)
-      st = MFMG_ERR_BREAKDOWN;
-    else if (S.rr0 > 0.0 && !(S.rr <= S.tol2))
-      st = MFMG_NOT_CONVERGED;
+    st = solve_status(S);
     if (stats) {
       stats->iters = S.iters;
       stats->status = st;
@@ -1889,7 +1950,9 @@ extern "C" mfmg_status mfmg_pcg_solve_adjoint(mfmg_hierarchy *h, const double *p
     return fail(MFMG_ERR_OOM, "host allocation failed");
   }
   if (st == MFMG_ERR_BREAKDOWN) return fail(st, "PCG breakdown: (r,z) or (p,Ap) not positive");
-  if (st == MFMG_NOT_CONVERGED) g_err = "not converged within max_iter";
+  if (st == MFMG_NOT_CONVERGED)
+    g_err = "not converged: the residual (recursive or true) is above rtol after max_iter "
+            "iterations or at the rounding floor";
   return st;
 }
 

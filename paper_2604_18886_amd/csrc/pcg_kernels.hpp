@@ -19,7 +19,20 @@ struct PcgArgs {
   double *partials;
   double *hist;
   int *host_done;        // pinned host copy of S->done (mapped), or null
+  int scale_low;         // 1: the cycle reads an FP32 copy of the residual, scaled
+                         // by the power of two S->rscale (0: FP64, unscaled)
 };
+
+// Scale of the cycle's FP32 input: the power of two that brings the mean
+// square of a residual with squared norm rr over n entries to [1, 4).  The
+// cycle is linear, so z = M r is recovered exactly by the inverse power of
+// two; FP32's range then holds the residual whatever the scale of the
+// right-hand side.
+__device__ __forceinline__ double low_scale(const PcgArgs &P, double rr) {
+  if (!P.scale_low || !(rr > 0.0) || !(rr < INFINITY)) return 1.0;
+  int e = ilogb(rr / (64.0 * double(P.T.nlb)));
+  return ldexp(1.0, -(e / 2));
+}
 
 __device__ __forceinline__ void leaf_cell(const PcgArgs &P, uint32_t b, int m, double &c,
                                           double &k0, double &k1, double &k2) {
@@ -198,17 +211,39 @@ __global__ void __launch_bounds__(kBlock) k_warm_start(PcgArgs P, const double *
   block_partial(part, P.partials);
 }
 
-// (r, z) over the leaf bricks (wave_loop grid)
+// r_low = V(r * S->rscale): the cycle's input after the residual was set
+// outside the iteration (start, warm start, restart)
+template <class V>
+__global__ void __launch_bounds__(kBlock) k_scale_low(PcgArgs P, const double *r, V *r_low) {
+  double sc = P.S->rscale;
+  LEAF_LOOP(P) { r_low[b * 64u + m] = V(r[b * 64u + m] * sc); }
+}
+
+// Restart from the true residual t (device order, already zero on inactive
+// cells): r = t and ||r||^2 (the stop test's reference ||r_0|| is kept)
+__global__ void __launch_bounds__(kBlock) k_restart(PcgArgs P, const double *t, double *r) {
+  double part = 0.0;
+  LEAF_LOOP(P) {
+    double v = t[b * 64u + m];
+    r[b * 64u + m] = v;
+    part += v * v;
+  }
+  block_partial(part, P.partials);
+}
+
+// (r, z) over the leaf bricks (wave_loop grid); z is the cycle's output for
+// the scaled residual
 template <class V>
 __global__ void __launch_bounds__(kBlock) k_pcg_rz(PcgArgs P, const double *r, const V *z) {
   if (P.S->done) return;
+  double zs = 1.0 / P.S->rscale;  // a power of two: exact
   uint32_t m = threadIdx.x & (kWave - 1);
   const __amdgpu_buffer_rsrc_t rr = make_rsrc(r, uint64_t(P.T.nlb) * 64 * sizeof(double));
   const __amdgpu_buffer_rsrc_t zr = make_rsrc(z, uint64_t(P.T.nlb) * 64 * sizeof(V));
   const WaveLoop W = wave_loop(P.T.nlb);
   double part = 0.0;
   for (uint32_t b = W.first; b < W.end; b += W.step)
-    part += bload<double>(rr, m, b * 64u) * double(bload<V>(zr, m, b * 64u));
+    part += bload<double>(rr, m, b * 64u) * (double(bload<V>(zr, m, b * 64u)) * zs);
   block_partial(part, P.partials);
 }
 
@@ -225,6 +260,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_p(PcgArgs P, const V *z, double 
   if (P.S->done) return;
   double beta = first ? 0.0 : P.S->beta;
   double alpha = P.S->alpha;
+  double zs = 1.0 / P.S->rscale;
   uint32_t m = threadIdx.x & (kWave - 1);
   const __amdgpu_buffer_rsrc_t zr = make_rsrc(z, uint64_t(P.T.nlb) * 64 * sizeof(V));
   const __amdgpu_buffer_rsrc_t pr = make_rsrc(p, uint64_t(P.T.nb) * 64 * sizeof(double));
@@ -232,7 +268,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_p(PcgArgs P, const V *z, double 
   const WaveLoop W = wave_loop(P.T.nlb);
   if (!first && blockIdx.x == 0 && threadIdx.x == 0) P.S->xpend = 0;
   for (uint32_t b = W.first; b < W.end; b += W.step) {
-    double v = double(bload<V>(zr, m, b * 64u));
+    double v = double(bload<V>(zr, m, b * 64u)) * zs;
     if (!first) {
       double po = bload<double>(pr, m, b * 64u);
       bstore<double>(xr, m, b * 64u, bload<double>(xr, m, b * 64u) + alpha * po);
@@ -295,6 +331,7 @@ enum FinishOp : int {
   kFinSum = 5,    // sum over active cells (null-space mean)
   kFinShift = 6,  // ||v||^2 after the mean shift, arg = mode of k_shift_mean
   kFinWarm = 7,   // ||rhs - A x0||^2 of a warm start (tolerance kept from ||rhs||)
+  kFinRestart = 8,// ||r||^2 of a restart from the true residual (tolerance kept)
 };
 
 __device__ __forceinline__ void finish_iteration(const PcgArgs &P, double tot) {
@@ -322,6 +359,7 @@ __device__ __forceinline__ void finish_initial(const PcgArgs &P, double tot, dou
   S->done = (tot == 0.0) || !(tot < INFINITY);
   if (!(tot < INFINITY)) S->status = -5;
   S->rz = 0.0;
+  S->rscale = low_scale(P, tot);
   P.hist[0] = tot > 0.0 ? 1.0 : 0.0;
 }
 
@@ -362,6 +400,9 @@ __global__ void __launch_bounds__(1024) k_finish(PcgArgs P, int64_t n, int op, i
       } else {
         S->alpha = S->rz / tot;
       }
+      // scale of the residual the update is about to write, from the last
+      // norm (a PCG residual changes by modest factors per iteration)
+      S->rscale = low_scale(P, S->rr);
       break;
     case kFinUpdate:
       finish_iteration(P, tot);
@@ -379,6 +420,7 @@ __global__ void __launch_bounds__(1024) k_finish(PcgArgs P, int64_t n, int op, i
       break;
     case kFinWarm:
       S->rr = tot;
+      S->rscale = low_scale(P, tot);
       P.hist[0] = S->rr0 > 0.0 ? sqrt(tot / S->rr0) : 0.0;
       if (!(tot < INFINITY)) {
         S->status = -5;
@@ -386,6 +428,13 @@ __global__ void __launch_bounds__(1024) k_finish(PcgArgs P, int64_t n, int op, i
       } else if (tot <= S->tol2) {
         S->done = 1;
       }
+      break;
+    case kFinRestart:
+      S->rr = tot;
+      S->rscale = low_scale(P, tot);
+      S->xpend = 0;
+      S->done = !(tot > S->tol2) || !(tot < INFINITY);
+      if (!(tot < INFINITY)) S->status = -5;
       break;
   }
   // the host polls the stop flag here instead of copying the scalars back
@@ -401,6 +450,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_update(PcgArgs P, double *r, V *
                                                        int64_t n2) {
   if (P.S->done) return;
   double alpha = P.S->alpha;
+  double sc = P.S->rscale;
   double part = 0.0;
   double2 *r2 = reinterpret_cast<double2 *>(r);
   const double2 *a2 = reinterpret_cast<const double2 *>(Ap);
@@ -411,8 +461,8 @@ __global__ void __launch_bounds__(kBlock) k_pcg_update(PcgArgs P, double *r, V *
     rv.y -= alpha * av.y;
     r2[i] = rv;
     if (r_low) {
-      r_low[2 * i] = V(rv.x);
-      r_low[2 * i + 1] = V(rv.y);
+      r_low[2 * i] = V(rv.x * sc);
+      r_low[2 * i + 1] = V(rv.y * sc);
     }
     part += rv.x * rv.x + rv.y * rv.y;
   }
@@ -550,13 +600,14 @@ __global__ void __launch_bounds__(kBlock) k_shift_mean(PcgArgs P, double *v, V *
                                                        double n_active, int mode) {
   if (mode == 1 && P.S->done) return;
   double mean = P.S->sum / n_active;
+  double sc = P.S->rscale;
   double part = 0.0;
   LEAF_LOOP(P) {
     const BrickMeta M = P.T.meta[b];
     uint32_t i = b * 64u + m;
     double x = ((act_mask(M) >> m) & 1ull) ? v[i] - mean : 0.0;
     v[i] = x;
-    if (v_low) v_low[i] = V(x);
+    if (v_low) v_low[i] = V(x * sc);
     part += x * x;
   }
   block_partial(part, P.partials);

@@ -131,6 +131,68 @@ def solid_sdf(cfg):
     return None
 
 
+# --------------------------------------------------------------------------
+# static projection test (tank with an obstacle, Section 4.4)
+
+
+def obstacle_level_set(name):
+    """Level set of the obstacle of the static projection test, positive in
+    the fluid: the sphere |x - c| - 0.25 or the star
+    r - (0.237 + 0.079 cos(6 theta) cos(6 phi)) about c = (1/2, 1/2, 1/2)
+    (Section 4.1), theta the polar angle from +z and phi the azimuth in the
+    x-y plane.  The sphere's is a signed distance; the star's is not."""
+    if name == "sphere":
+        def phi(x, y, z):
+            return np.sqrt((x - 0.5) ** 2 + (y - 0.5) ** 2 + (z - 0.5) ** 2) - 0.25
+        return phi, True
+    if name == "star":
+        def phi(x, y, z):
+            dx, dy, dz = x - 0.5, y - 0.5, z - 0.5
+            r = np.sqrt(dx * dx + dy * dy + dz * dz)
+            theta = np.arccos(np.clip(dz / np.maximum(r, 1e-300), -1.0, 1.0))
+            az = np.arctan2(dy, dx)
+            return r - (0.237 + 0.079 * np.cos(6.0 * theta) * np.cos(6.0 * az))
+        return phi, False
+    raise ValueError(name)
+
+
+def tank_spec(root_level, obstacle):
+    """Octree of the static projection test: root cells of level root_level,
+    two levels finer where a 4^3 node meets the obstacle's surface (the
+    sphere of radius 1/4), or, for the star, the spherical shell
+    0.158 <= |x - c| <= 0.316 that contains its surface (the refinement
+    predicates are closed-form tests on node boxes)."""
+    if obstacle == "sphere":
+        prim = sphere_prim((0.5, 0.5, 0.5), 0.25, 0.0)
+    elif obstacle == "star":
+        prim = sphere_prim((0.5, 0.5, 0.5), 0.237, 0.079)
+    else:
+        raise ValueError(obstacle)
+    return {"min_level": root_level, "max_level": root_level + 2, "node_size": NODE_SIZE,
+            "prims": [prim]}
+
+
+def tank_bc():
+    """Solid floor and sides (Neumann), open top y = 1 (Dirichlet p = 0 on
+    the face)."""
+    return [NEUMANN, NEUMANN, NEUMANN, DIRICHLET, NEUMANN, NEUMANN], 0.5
+
+
+def tank_beta(obstacle, face_level, face_ijk, face_dir):
+    """Fluid face fractions of the obstacle (no jitter)."""
+    phi, is_sdf = obstacle_level_set(obstacle)
+    return face_fractions(face_level, face_ijk, face_dir, phi, lipschitz=is_sdf)
+
+
+def tank_velocity(face_dir, face_kind, bc):
+    """MAC face velocities of the uniform downward flow (0, -1, 0): -1 on
+    faces normal to y, 0 on the others and on solid (Neumann) walls."""
+    d = np.asarray(face_dir)
+    u = np.where((d >> 1) == 1, -1.0, 0.0)
+    u[(np.asarray(face_kind) == 0) & (np.asarray(bc)[d] == NEUMANN)] = 0.0
+    return u
+
+
 def _triangle_positive_fraction(a, b, c):
     """Fraction of a triangle on which the linear interpolant of the vertex
     values (a, b, c) is strictly positive (vectorised, exact)."""
@@ -176,16 +238,17 @@ def face_corners(level, ijk, direction):
     return corners
 
 
-def face_fractions(level, ijk, direction, sdf, chunk=1 << 21):
+def face_fractions(level, ijk, direction, sdf, chunk=1 << 21, lipschitz=True):
     """Fluid fraction of each face: the face square is split along its
     (lo,lo)-(hi,hi) diagonal into two triangles; on each, the signed
     distance is interpolated linearly from its corners and the area where
     it is positive is measured exactly.
 
-    The signed distance is 1-Lipschitz, so a face whose centre lies farther
+    A signed distance is 1-Lipschitz, so a face whose centre lies farther
     than its half-diagonal (h / sqrt 2) from the interface has four corners
     of one sign: its fraction is exactly 1 or 0 and its corners are not
-    evaluated."""
+    evaluated.  For a level set that is not a distance (lipschitz=False)
+    every face's corners are evaluated."""
     level = np.asarray(level)
     F = len(level)
     out = np.ones(F)
@@ -202,7 +265,7 @@ def face_fractions(level, ijk, direction, sdf, chunk=1 << 21):
         rows = np.arange(e - s)
         ctr[rows, d // 2] += (d % 2 - 0.5) * h
         pc = sdf(ctr[:, 0], ctr[:, 1], ctr[:, 2])
-        far = np.abs(pc) > 0.7072 * h
+        far = (np.abs(pc) > 0.7072 * h) if lipschitz else np.zeros(len(pc), dtype=bool)
         res = np.where(pc > 0, 1.0, 0.0)
         near = np.nonzero(~far)[0]
         if len(near):
@@ -327,13 +390,14 @@ def adjoint_target(leaf_level, leaf_ijk, pmax, seed=1005 + 29):
     return out
 
 
-def sample_faces(n_faces, special, count=50, seed=1005 + 31):
+def sample_faces(n_faces, special, count=50, seed=1005 + 31, pool=None):
     """Half of ``count`` faces drawn from ``special`` (indices where the
-    operator is non-symmetric or beta < 1), half uniformly from all."""
+    operator is non-symmetric or beta < 1), half uniformly from ``pool``
+    (default: all faces)."""
     rng = np.random.default_rng(seed)
     special = np.asarray(special)
     k = min(count // 2, len(special))
     a = rng.choice(special, size=k, replace=False) if k else np.zeros(0, int)
-    rest = np.setdiff1d(np.arange(n_faces), a)
+    rest = np.setdiff1d(np.arange(n_faces) if pool is None else np.asarray(pool), a)
     b = rng.choice(rest, size=count - k, replace=False)
     return np.sort(np.concatenate([a, b]).astype(np.int64))

@@ -26,19 +26,30 @@ def _loss_grad(case, p):
     return np.where(case.disc.active, 2.0 * (p - pt), 0.0), pt
 
 
-def test_transposed_cycle_matches_oracle(case):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_transposed_cycle_matches_oracle(case, precision):
+    """M^T against the oracle's transposed cycle (FP64; mixed: on the
+    coefficients the mixed store keeps), and x . M y = y . M^T x on the
+    device: the transposed cycle divides by the diagonal the forward
+    half-sweeps use, so M^T is the transpose of the mixed M too, up to
+    FP32 rounding."""
     from paper_2604_18886_amd import mfmg
-    h = case.gpu_hierarchy()
+    h = case.gpu_hierarchy(precision=precision)
     rng = np.random.default_rng(21)
     r = np.where(case.disc.active, rng.uniform(-1, 1, case.T.n), 0.0)
     z = mfmg.apply_precond(h, case.device(r), transpose=True).cpu().numpy()
-    want = case.hier.vcycle_T(r)
-    assert rel(z, want) <= 1e-12
+    H = case.hier if precision == 0 else case.hier.stored_precision()
+    want = H.vcycle_T(r)
+    tol = 1e-12 if precision == 0 else 1e-5
+    assert rel(z, want) <= tol
     # adjoint identity on the device: x . M y == y . M^T x
     y = np.where(case.disc.active, rng.uniform(-1, 1, case.T.n), 0.0)
     My = mfmg.apply_precond(h, case.device(y)).cpu().numpy()
     MTx = mfmg.apply_precond(h, case.device(r), transpose=True).cpu().numpy()
-    assert abs(r @ My - y @ MTx) <= 1e-12 * (abs(r @ My) + abs(y @ MTx))
+    gap = abs(r @ My - y @ MTx) / (abs(r @ My) + abs(y @ MTx))
+    print(f"  precision={precision}: M^T vs oracle {rel(z, want):.2e}, "
+          f"x.My - y.M^Tx {gap:.2e}", flush=True)
+    assert gap <= (1e-12 if precision == 0 else 1e-5)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -57,7 +68,7 @@ def test_adjoint_solve_and_gradient(case, precision):
     print(f"  precision={precision} adjoint iters={ast['iters']} oracle={info['iters']} "
           f"true={ast['rel_resid_true']:.2e} lam err={rel(lam, lam_o):.2e} "
           f"grad err={rel(grad, grad_o):.2e}", flush=True)
-    assert ast["status"] == 0 and ast["rel_resid_true"] <= 1.5e-12
+    assert ast["status"] == 0 and ast["rel_resid_true"] <= 1e-12
     assert rel(lam, lam_o) <= 1e-9
     assert np.abs(grad - grad_o).max() <= 1e-9 * np.abs(grad_o).max()
     if precision == 0:
@@ -82,8 +93,8 @@ def test_gradient_against_finite_differences(precision):
     grad = grad_d.cpu().numpy()
     both = d.active[d.face_owner] & ((d.face_other < 0) | d.active[np.maximum(d.face_other, 0)])
     special = np.nonzero(((d.face_kind == D.COARSE) | (case.beta < 1)) & both)[0]
-    faces = problems.sample_faces(d.n_faces, special, count=50)
-    faces = faces[both[faces]]
+    faces = problems.sample_faces(d.n_faces, special, count=50, pool=np.nonzero(both)[0])
+    assert len(faces) == 50 and np.all(both[faces])
 
     def factory(bb):
         dd = D.Discretization(case.T, None, case.bc, case.theta)

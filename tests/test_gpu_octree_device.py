@@ -163,4 +163,4 @@ def test_rebuilds_around_a_moving_sphere():
         res = np.linalg.norm(r) / np.linalg.norm(np.where(act, rhs, 0.0))
         print(f"  step {step}: {td.n_leaves} leaves, {st['iters']} iterations, "
               f"oracle-measured residual {res:.2e}", flush=True)
-        assert st["status"] == 0 and res <= 1.5e-10
+        assert st["status"] == 0 and res <= 1e-10 * (1 + 1e-4)

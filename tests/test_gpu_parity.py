@@ -82,15 +82,24 @@ def test_one_cycle_fp64(case):
     assert rel(z, want) <= 1e-12
 
 
-def test_one_cycle_mixed_close(case):
+def test_one_cycle_mixed_against_stored_precision_oracle(case):
+    """The mixed cycle (FP32 values, FP32 leaf / FP16 inner coefficients)
+    against the oracle's FP64 cycle on the coefficients that store keeps
+    (Hierarchy.stored_precision): what is left is FP32 arithmetic (and the
+    FP32 rounding of the input), about 1e-6 relative.  The coefficient
+    rounding alone moves the cycle by far more on the jittered families,
+    so a defect in the FP32/FP16 kernels larger than FP32 rounding fails."""
     from paper_2604_18886_amd import mfmg
     h = case.gpu_hierarchy(precision=mfmg.MIXED)
     rng = np.random.default_rng(9)
     r = np.where(case.disc.active, rng.uniform(-1, 1, case.T.n), 0.0)
     z = mfmg.apply_precond(h, case.device(r)).cpu().numpy()
-    want = case.hier.vcycle(r)
-    # FP32 arithmetic with FP16 coarse coefficients: a perturbed preconditioner
-    assert rel(z, want) <= 2e-2
+    want = case.hier.stored_precision().vcycle(r)
+    err = rel(z, want)
+    moved = rel(case.hier.vcycle(r), want)
+    print(f"  mixed cycle vs stored-precision oracle {err:.2e} (rounding of the "
+          f"coefficients alone: {moved:.2e})", flush=True)
+    assert err <= 1e-5
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -103,7 +112,7 @@ def test_solve_matches_oracle(case, precision):
     print(f"  precision={precision} gpu iters={st['iters']} oracle(1e-13) iters={info['iters']}"
           f" true={st['rel_resid_true']:.2e} err={rel(p, x):.2e}", flush=True)
     assert st["status"] == 0
-    assert st["rel_resid_true"] <= 1.5e-10
+    assert st["rel_resid_true"] <= 1e-10  # the true residual meets rtol
     assert rel(p, x) <= 1e-9
     # iteration count of the FP64 path equals the oracle's at the same rtol
     if precision == 0:
@@ -188,7 +197,7 @@ def test_warm_start_matches_oracle(precision):
     p = p.cpu().numpy()
     print(f"  precision={precision} warm: gpu iters={st['iters']} oracle={iw['iters']} "
           f"true={st['rel_resid_true']:.2e} err={rel(p, xs):.2e}", flush=True)
-    assert st["status"] == 0 and st["rel_resid_true"] <= 1.5e-10
+    assert st["status"] == 0 and st["rel_resid_true"] <= 1e-10
     assert rel(p, xs) <= 1e-9
     if precision == 0:
         assert abs(st["iters"] - iw["iters"]) <= 1

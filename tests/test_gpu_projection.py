@@ -72,9 +72,9 @@ def test_static_tank_projection(tank, precision):
           f"(oracle 1e-13 solve: {rms_ref:.3e}); p err {rel(pg, x):.2e}", flush=True)
     assert st["status"] == 0
     assert rms0 == pytest.approx(PJ.rms_divergence(tank.disc, div_ref), rel=1e-13)
-    # RMS_V weighs r_i^2 / V_i: against the 2-norm of the residual (<= 1.5e-10
+    # RMS_V weighs r_i^2 / V_i: against the 2-norm of the residual (<= 1e-10
     # relative) the ratio can grow by sqrt(V_max / V_min) = 8 on levels 4..6
-    assert rms1 <= 8 * 1.5e-10 * rms0
+    assert rms1 <= 8 * 1e-10 * (1 + 1e-4) * rms0
     assert rel(pg, x) <= 1e-9
     # F / (beta h^2) is a pressure difference over h: the update differs from
     # the oracle's by at most 2 max|dp| / h_min
