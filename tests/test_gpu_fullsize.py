@@ -7,10 +7,11 @@ benchmark times (default hierarchy, rtol 1e-10, FP64 and mixed cycle):
 * the adjoint on the 6..9 cut-cell octree: lambda and dL/dbeta against the
   oracle's adjoint solve and per-face gradient;
 * leaf levels 7..10 (26.3M leaves): topology bit-exact against the oracle
-  octree and faces, and the relative residual of both GPU solutions
-  measured with the oracle's assembled operator (the oracle's own solve at
-  this size is left to the benchmark's bounded sample); the same octree
-  built on the device, bit-exact against the oracle too.
+  octree and faces, the relative residual of both GPU solutions measured
+  with the oracle's assembled operator, and both solutions against the
+  oracle's p* (1e-13) at 32768 seeded leaves and in the 2-norm (the sample
+  is stored, the full oracle solve takes minutes); the same octree built
+  on the device, bit-exact against the oracle too.
 """
 
 import numpy as np
@@ -77,7 +78,8 @@ def test_full_solve_matches_oracle(full, precision):
           flush=True)
     assert st["status"] == 0
     assert st["rel_resid_true"] <= 1e-10
-    assert res <= 1.5e-10
+    # the same residual summed in another order: ~1e-16 |A p| / |r| apart
+    assert res <= 1e-10 * (1 + 1e-4)
     assert err <= 1e-9
     assert np.all(p[~full.disc.active] == 0.0)
 
@@ -89,11 +91,14 @@ def test_full_adjoint_matches_oracle(precision):
     from paper_2604_18886_amd import mfmg
     case = _case(3)
     h = case.gpu_hierarchy(precision=precision)
-    p_d, _ = mfmg.pcg_solve(h, case.device(case.rhs), rtol=1e-12)
+    p_d, _ = mfmg.pcg_solve(h, case.device(case.rhs), rtol=1e-11)
     p = p_d.cpu().numpy()
     pt = problems.adjoint_target(case.T.level, case.T.ijk, np.abs(p).max())
     g = np.where(case.disc.active, 2.0 * (p - pt), 0.0)
-    lam_d, grad_d, st = mfmg.pcg_solve_adjoint(h, p_d, case.device(g), rtol=1e-12)
+    # rtol 1e-11: at 2.3M cells the FP64 evaluation of ||g - A^T lambda||
+    # itself rounds to about 1e-12 of ||g|| (about eps |A| |lambda|), so a
+    # tolerance of 1e-12 is below what any iterate can show
+    lam_d, grad_d, st = mfmg.pcg_solve_adjoint(h, p_d, case.device(g), rtol=1e-11)
     if not hasattr(case, "lam13"):
         case.lam13, _ = K.pcg(case.disc.A.T.tocsr(), g, case.hier.vcycle_T, 1e-13, 400,
                               active=case.disc.active)
@@ -103,19 +108,32 @@ def test_full_adjoint_matches_oracle(precision):
     print(f"  precision={precision} adjoint iters={st['iters']} true={st['rel_resid_true']:.2e} "
           f"lam err={rel(lam, case.lam13):.2e} "
           f"grad err={np.abs(grad - grad_o).max() / np.abs(grad_o).max():.2e}", flush=True)
-    # rtol bounds the recursively updated residual; at 2.3M cells the true
-    # residual of the FP64 iteration settles a few times above it
+    # a converged solve meets rtol in its true residual (the iteration
+    # restarts from the true residual while it does not)
     assert st["status"] == 0 and st["rel_resid_true"] <= 1e-11
     assert rel(lam, case.lam13) <= 1e-9
     assert np.abs(grad - grad_o).max() <= 1e-9 * np.abs(grad_o).max()
 
 
+def _large_sample():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "large_workload_solution_sample.npz")
+    with np.load(path, allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
 def test_largest_workload_topology_and_residual():
     """26.3M leaves: leaves and faces bit-exact against the oracle; both
-    GPU solutions have oracle-measured relative residual <= 1.5e-10 and
-    agree with each other."""
+    GPU solutions have oracle-measured relative residual <= 1e-10, agree
+    with each other, and with the oracle's solution p* at 1e-13 to 1e-9
+    relative L2 over 32768 seeded active leaves (p* sampled by the
+    committed tests/golden/make_large_workload_sample.py; the full oracle
+    solve takes minutes) and in the full 2-norm."""
     from paper_2604_18886_amd import mfmg
     case = _case(4)
+    ref = _large_sample()
+    assert int(ref["n_leaves"]) == case.T.n
+    assert np.all(case.disc.active[ref["idx"]])
     print(f"  {case.T.n} leaves, {case.disc.n_faces} faces", flush=True)
     _topology_equal(case)
     sols = []
@@ -124,10 +142,14 @@ def test_largest_workload_topology_and_residual():
         p_d, st = mfmg.pcg_solve(h, case.device(case.rhs), rtol=1e-10)
         p = p_d.cpu().numpy()
         res = _oracle_resid(case, p)
+        err = rel(p[ref["idx"]], ref["val"])
+        nerr = abs(np.linalg.norm(p) - float(ref["norm"])) / float(ref["norm"])
         print(f"  precision={precision} iters={st['iters']} gpu true={st['rel_resid_true']:.2e} "
-              f"oracle-measured={res:.2e}", flush=True)
-        assert st["status"] == 0
-        assert res <= 1.5e-10
+              f"oracle-measured={res:.2e} err vs p* (sampled)={err:.2e} norm diff={nerr:.2e}",
+              flush=True)
+        assert err <= 1e-9 and nerr <= 1e-9
+        assert st["status"] == 0 and st["rel_resid_true"] <= 1e-10
+        assert res <= 1e-10 * (1 + 1e-4)
         sols.append(p)
         del h
     assert rel(sols[1], sols[0]) <= 1e-8
@@ -189,4 +211,4 @@ def test_offset_limit_and_largest_mixed_solve():
     p, st = mfmg.pcg_solve(h, rhs, rtol=1e-10)
     print(f"  mixed: {st['iters']} iterations, true residual {st['rel_resid_true']:.2e}, "
           f"{st['seconds'] * 1e3:.1f} ms", flush=True)
-    assert st["status"] == 0 and st["rel_resid_true"] <= 1.5e-10
+    assert st["status"] == 0 and st["rel_resid_true"] <= 1e-10
