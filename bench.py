@@ -131,9 +131,25 @@ def summarize_pmc(fetch_csv, write_csv, level):
     return precisions.pop(), rec
 
 
-def cpu_baseline(sample_levels=(6, 9)):
-    """The oracle (test infrastructure) timed on the host, one thread, on a
-    smaller member of the same workload family."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, iters_full, n_iter=2):
+    """The oracle (test infrastructure) timed on the host, one thread, on the
+    benchmark's own workload: its octree, discretisation and hierarchy are
+    built (not timed), then PCG is run for n_iter iterations (n_iter + 1
+    cycles and operator applications with the initial cycle and the final
+    true residual); the full solve's time is that scaled to the iters_full
+    iterations the solve to 1e-10 takes, i.e. (iters_full + 1) / (n_iter + 1)
+    times the measured time."""
     from threadpoolctl import threadpool_limits
 
     import problems
@@ -142,23 +158,59 @@ def cpu_baseline(sample_levels=(6, 9)):
     from oracle import multigrid as M
     from oracle import octree as O
 
-    spec = problems.config_spec(4, *sample_levels)
+    t0 = time.perf_counter()
+    spec = problems.config_spec(cfg)
     T = O.Octree(spec)
-    bc, th = problems.config_bc(4)
+    bc, th = problems.config_bc(cfg)
     disc = D.Discretization(T, None, bc, th)
-    disc.set_beta(problems.face_beta(4, disc.face_level, disc.face_ijk, disc.face_dir))
-    rhs = problems.rhs_random(4, T.level, T.ijk)
+    disc.set_beta(problems.face_beta(cfg, disc.face_level, disc.face_ijk, disc.face_dir))
+    rhs = problems.rhs_random(cfg, T.level, T.ijk)
     H = M.Hierarchy(disc)
+    setup = time.perf_counter() - t0
+    log(f"[bench] oracle set up in {setup:.0f} s; timing {n_iter} PCG iterations")
     with threadpool_limits(1):
         t0 = time.perf_counter()
-        _, info = K.pcg(disc.A, rhs, H.vcycle, 1e-10, 200, active=disc.active)
+        K.pcg(disc.A, rhs, H.vcycle, 1e-10, n_iter, active=disc.active)
         dt = time.perf_counter() - t0
     nact = int(disc.active.sum())
-    return {"value": nact / dt / 1e6, "unit": "Mcells/s", "cores": 1, "kind": "oracle",
-            "sample": (f"same workload family at leaf levels {sample_levels[0]}.."
-                       f"{sample_levels[1]} ({T.n} leaves, {nact} active), one full solve "
-                       f"to 1e-10 ({info['iters']} iterations, {dt:.1f} s), "
-                       f"NumPy/SciPy FP64, 1 thread of {os.cpu_count()}")}
+    full = dt * (iters_full + 1) / (n_iter + 1)
+    return {"value": nact / full / 1e6, "unit": "Mcells/s", "cores": 1, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "sample": (f"the benchmark's workload ({T.n} leaves, {nact} active): {n_iter} PCG "
+                       f"iterations of the oracle ({n_iter + 1} cycles and operator "
+                       f"applications) in {dt:.1f} s, scaled to the {iters_full} iterations of "
+                       f"the solve to 1e-10 ({full:.0f} s); NumPy/SciPy FP64, 1 thread of "
+                       f"{os.cpu_count()} ({cpu_model()}); octree, discretisation and "
+                       f"hierarchy built beforehand in {setup:.0f} s")}
+
+
+def oracle_sample(cfg):
+    """The oracle's solution of the workload at relative residual 1e-13,
+    sampled at seeded active leaves (written by
+    tests/golden/make_large_workload_sample.py), or None."""
+    if cfg != 4:
+        return None
+    path = os.path.join(ROOT, "tests", "golden", "large_workload_solution_sample.npz")
+    if not os.path.exists(path):
+        return None
+    import numpy as np
+    with np.load(path, allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
+def error_vs_oracle(p, sample):
+    """Relative L2 error of the solution p (device tensor, canonical order)
+    against the oracle's p* over the sampled leaves, and the relative
+    difference of the full 2-norms."""
+    import numpy as np
+    import torch
+    idx = torch.as_tensor(sample["idx"], device=p.device)
+    got = p[idx].cpu().numpy()
+    want = sample["val"]
+    return {"rel_l2_sampled": float(np.linalg.norm(got - want) / np.linalg.norm(want)),
+            "rel_norm_diff": float(abs(torch.linalg.norm(p).item() - float(sample["norm"]))
+                                   / float(sample["norm"])),
+            "samples": int(len(want)), "oracle_rtol": float(sample["rtol"])}
 
 
 def projection_timing(mfmg, torch, h, beta_d, fdir, kind, bc, reps=5):
@@ -200,6 +252,119 @@ def projection_timing(mfmg, torch, h, beta_d, fdir, kind, bc, reps=5):
     return {"divergence_ms": ms_div, "update_ms": ms_upd, "projection_ms": total,
             "iters": st["iters"], "rms_div_before": rms0, "rms_div_after": rms1,
             "field": "u = (0, -1, 0), zero on solid walls", "rtol": 1e-10}
+
+
+def fit_slope(x, y):
+    """Least-squares slope of log2(y) against x."""
+    import numpy as np
+    x = np.asarray(x, dtype=np.float64)
+    ly = np.log2(np.asarray(y, dtype=np.float64))
+    return float(np.polyfit(x, ly, 1)[0])
+
+
+def static_projection(mfmg, torch, obstacle, root_level, rtol=1e-6, mu=2, sweep_iters=8):
+    """The static projection test (Section 4.4) on one grid: tank with solid
+    floor and sides and an open top, a solid sphere or star at the centre,
+    u = (0, -1, 0); mixed-precision hierarchy with the mu-cycle, PCG to rtol.
+    The discrete solution is p = y - 1 exactly (the discretisation
+    reproduces linear fields), so the pressure error and the velocity left
+    after the update measure the solve alone.  RMS_V of the divergence in
+    two readings: of div_i / V_i (the divergence density) and of the
+    integrated divergence div_i (a flux)."""
+    import numpy as np
+    import problems
+    spec = problems.tank_spec(root_level, obstacle)
+    bc, theta = problems.tank_bc()
+    t0 = time.perf_counter()
+    tree = mfmg.build_octree(spec, device=True)
+    lev, ijk = tree.leaves()
+    owner, fdir, other, kind = tree.faces()
+    beta = problems.tank_beta(obstacle, lev[owner], ijk[owner], fdir)
+    u0 = problems.tank_velocity(fdir, kind, bc)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    beta_d, u0_d = dev(beta), dev(u0)
+    del beta, u0, owner, other, kind
+    co = mfmg.assemble_coeffs(tree, beta_d, bc, theta)
+    h = mfmg.build_hierarchy(co, precision=mfmg.MIXED, mu=mu)
+    act = (co.leaf_coeffs()[0] != 0)
+    hl = torch.as_tensor(np.ldexp(1.0, -lev.astype(np.int64)), device="cuda")
+    V = hl ** 3
+    y = torch.as_tensor((ijk[:, 1] + 0.5), dtype=torch.float64, device="cuda") * hl
+    setup = time.perf_counter() - t0
+
+    def rms_flux(div):
+        return float(torch.sqrt((V * div * div)[act].sum() / V[act].sum()))
+
+    div0 = mfmg.divergence(h, beta_d, u0_d)
+    rms0 = mfmg.divergence_rms(h, div0)
+    rms0_flux = rms_flux(div0)
+    mfmg.pcg_solve(h, div0, rtol=rtol)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p, st, hist = mfmg.pcg_solve(h, div0, rtol=rtol, history=True)
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t0
+    u = u0_d.clone()
+    mfmg.project_velocity(h, beta_d, p, u)
+    div1 = mfmg.divergence(h, beta_d, u)
+    fluid = beta_d > 0
+    perr = float(torch.abs(p - (y - 1.0))[act].max())
+    out = {"obstacle": obstacle, "root_level": root_level, "levels": [root_level, root_level + 2],
+           "leaves": tree.n_leaves, "active": int(act.sum()), "setup_s": setup,
+           "iters": st["iters"], "status": st["status"], "solve_ms": t_solve * 1e3,
+           "residual_history": [float(v) for v in hist],
+           "reduction_factor": 2.0 ** -fit_slope(range(1, len(hist)), hist[1:]),
+           "rms_div_before": rms0, "rms_div_after": mfmg.divergence_rms(h, div1),
+           "rms_flux_before": rms0_flux, "rms_flux_after": rms_flux(div1),
+           "p_max_err_vs_exact": perr,
+           "u_max_after": float(torch.abs(u[fluid]).max())}
+    if sweep_iters:
+        # RMS of the divergence left after a projection with k iterations
+        per = []
+        for k in range(1, sweep_iters + 1):
+            pk, _ = mfmg.pcg_solve(h, div0, rtol=0.0, max_iter=k)
+            uk = u0_d.clone()
+            mfmg.project_velocity(h, beta_d, pk, uk)
+            dk = mfmg.divergence(h, beta_d, uk)
+            per.append({"iters": k, "rms_div": mfmg.divergence_rms(h, dk),
+                        "rms_flux": rms_flux(dk),
+                        "p_max_err_vs_exact": float(torch.abs(pk - (y - 1.0))[act].max())})
+        out["per_iteration"] = per
+    del h, co, tree
+    return out
+
+
+def projection_study(mfmg, torch, roots=None):
+    """The static projection test over root cell sizes 1/16 .. 1/256 (sphere)
+    and 1/16 .. 1/128 (star, whose refined shell is larger), with fitted
+    orders of the RMS divergence left at rtol 1e-6 and the residual
+    reduction factors, next to the paper's figures (context)."""
+    import warnings
+    roots = roots or {"sphere": [4, 5, 6, 7, 8], "star": [4, 5, 6, 7]}
+    res = {"paper": {"rms_div_order": {"sphere": 2.54, "star": 2.27},
+                     "reduction_factor": {"sphere 256~1024": 7.16, "star 64~256": 5.17,
+                                          "star 256~1024": 5.88},
+                     "precision": "FP32 with FP64 dot products, rtol 1e-6, mu = 2"},
+           "runs": []}
+    for obstacle, levels in roots.items():
+        for l0 in levels:
+            with warnings.catch_warnings():
+                warnings.simplefilter("ignore")
+                r = static_projection(mfmg, torch, obstacle, l0)
+            log(f"[bench] static projection {obstacle} root 1/{2 ** l0} (levels {l0}..{l0 + 2}, "
+                f"{r['leaves']} leaves): {r['iters']} iterations, reduction factor "
+                f"{r['reduction_factor']:.2f}, RMS_V div {r['rms_div_before']:.3e} -> "
+                f"{r['rms_div_after']:.3e} (flux {r['rms_flux_before']:.3e} -> "
+                f"{r['rms_flux_after']:.3e}), max |p - (y - 1)| {r['p_max_err_vs_exact']:.2e}, "
+                f"max |u| {r['u_max_after']:.2e}, solve {r['solve_ms']:.1f} ms")
+            res["runs"].append(r)
+        runs = [r for r in res["runs"] if r["obstacle"] == obstacle]
+        x = [-r["root_level"] for r in runs]  # log2 of the root cell size
+        res.setdefault("rms_div_order", {})[obstacle] = fit_slope(
+            x, [r["rms_div_after"] for r in runs])
+        res.setdefault("rms_flux_order", {})[obstacle] = fit_slope(
+            x, [r["rms_flux_after"] for r in runs])
+    return res
 
 
 def rebuild_timing(mfmg, torch, spec, beta_d, bc, theta, reps=3):
@@ -247,6 +412,8 @@ def main():
     ap.add_argument("--traffic-fp64", action="store_true",
                     help="with --traffic-pass: the FP64 hierarchy's half-sweep instead")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
+    ap.add_argument("--projection-study", action="store_true",
+                    help="only the static projection test over root cell sizes (one JSON line)")
     args = ap.parse_args()
     if args.summarize_pmc:
         spec = __import__("problems").config_spec(args.workload)
@@ -275,6 +442,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
+    if args.projection_study:
+        print(json.dumps({"static_projection": projection_study(mfmg, torch)}), flush=True)
+        return
     cfg = args.workload
     spec = problems.config_spec(cfg)
     bc, theta = problems.config_bc(cfg)
@@ -319,6 +489,8 @@ def main():
         f"{time.perf_counter() - t0:.1f} s")
     out = {}
     sols = {}
+    errs = {}
+    sample = oracle_sample(cfg)
     p = torch.empty_like(rhs_d)
     for name, h in hiers.items():
         for _ in range(args.warmup):
@@ -336,6 +508,10 @@ def main():
         ms_c, by_c = mfmg.profile(h, mfmg.PROFILE_CYCLE, 0, reps=10)
         ms_cp, by_cp = mfmg.profile(h, mfmg.PROFILE_COPY, 0, reps=20)
         sols[name] = p.clone()
+        if sample is not None:
+            errs[name] = error_vs_oracle(p, sample)
+            log(f"[bench] {name}: relative L2 error against the oracle's p* (1e-13) over "
+                f"{errs[name]['samples']} sampled leaves {errs[name]['rel_l2_sampled']:.2e}")
         # adjoint of L = ||p - p_t||^2 at this solution (outside the timed region)
         pn = p.cpu().numpy()
         pt = problems.adjoint_target(lev, ijk, np.abs(pn).max())
@@ -399,7 +575,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample ...")
-        cpu = cpu_baseline()
+        cpu = cpu_baseline(cfg, out["fp64"]["iters"])
         log(f"[bench] cpu baseline {cpu['value']:.3f} Mcells/s")
     res = {
         "metric": METRIC,
@@ -423,7 +599,11 @@ def main():
             "rtol": 1e-10, "cycle": "FAS-style V-cycle, RBGS 2+2, coarsest 10 at level 3",
             "precision": "FP64 PCG; cycle FP32 with FP32 leaf / FP16 inner coefficients",
         },
+        "T_iter": head["mcells_per_s"] * head["iters"],
+        "rel_l2_vs_oracle": errs.get("mixed"),
         "fp64": {"value": out["fp64"]["mcells_per_s"], "ms_per_step": out["fp64"]["ms_per_solve"],
+                 "T_iter": out["fp64"]["mcells_per_s"] * out["fp64"]["iters"],
+                 "rel_l2_vs_oracle": errs.get("fp64"),
                  "iters": out["fp64"]["iters"], "rel_resid_true": out["fp64"]["rel_resid_true"],
                  "vcycle_gbs": out["fp64"]["cycle_gbs"], "vcycle_ms": out["fp64"]["cycle_ms"],
                  "vcycle_frac_of_peak": out["fp64"]["cycle_gbs"] / HBM_PEAK_GBS,
