@@ -313,6 +313,21 @@ mfmg_status mfmg_project_velocity(mfmg_hierarchy *h, const double *face_beta,
 mfmg_status mfmg_divergence_rms(mfmg_hierarchy *h, const double *div, double *rms,
                                 void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight time-stepping loops, harnesses that forbid allocation):
+ * mfmg_divergence_rms with its partial sums in a fixed array of the
+ * library's (2 x 2048 doubles = 32 KiB per device, held until the process
+ * ends) instead of the hierarchy's work buffers.  rms is a device pointer to
+ * one double, written by the last kernel queued on stream; the call
+ * allocates nothing, copies nothing and does not wait for the stream.  The
+ * device current at the call must be the hierarchy's; the array's device
+ * address is looked up on the first call on each device.  Every call on a
+ * device shares that device's array, so calls that overlap on one device
+ * (other streams, other threads) race.  Errors: INVALID_ARG (NULL argument,
+ * or a reduction grid larger than the array, which the fixed grid of at
+ * most 2048 workgroups never needs), HIP. */
+mfmg_status mfmg_divergence_rms_noalloc(mfmg_hierarchy *h, const double *div, double *rms,
+                                        void *stream);
 
 /* ------------------------------------------------ component entry points
  * For parity tests of single steps.  Device vectors of n_leaves doubles. */

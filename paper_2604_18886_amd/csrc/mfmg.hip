@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -2140,5 +2141,86 @@ extern "C" mfmg_status mfmg_divergence_rms(mfmg_hierarchy *h, const double *div,
   } catch (const HipError &e) {
     return hip_fail(e);
   }
+  return MFMG_OK;
+}
+
+// --------------------------------------------------------------------------
+// allocation-free form of mfmg_divergence_rms (callers that cannot allocate)
+// --------------------------------------------------------------------------
+namespace {
+
+// The partial sums of the two reductions (sum V (div/V)^2 and sum V), one
+// slot per workgroup of the reduction grid (at most kMaxReduceBlocks each),
+// in a fixed device array: 32 KiB that every device the library runs on
+// holds until the process ends.  Every slot a call reads is written by the
+// same call, so nothing needs clearing; calls that overlap on one device
+// race on it.
+constexpr int64_t kNoAllocSlots = 2 * kMaxReduceBlocks;
+__device__ __align__(256) double scratch[kNoAllocSlots];
+
+// Device address of `scratch` per device ordinal, looked up once per device
+// with that device current (in host code the array's name is only a
+// host-side stand-in).
+std::mutex g_scratch_mu;
+std::vector<double *> g_scratch_dev;
+
+hipError_t scratch_address(double **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (size_t(dev) >= g_scratch_dev.size()) g_scratch_dev.resize(size_t(dev) + 1, nullptr);
+  if (!g_scratch_dev[size_t(dev)]) {
+    double *ptr = nullptr;
+    e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[size_t(dev)] = ptr;
+  }
+  *out = g_scratch_dev[size_t(dev)];
+  return hipSuccess;
+}
+
+// rms = sqrt(a / b) from the n partials of each sum (a at parts, b at
+// parts + kMaxReduceBlocks), added in the order k_finish adds them.
+__global__ void __launch_bounds__(1024) k_rms_finish(const double *parts, int64_t n,
+                                                     double *rms) {
+  __shared__ double red[2][16];
+  double s[2];
+  for (int k = 0; k < 2; ++k) {
+    double v = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) v += parts[k * kMaxReduceBlocks + i];
+    s[k] = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[k][threadIdx.x >> 6] = s[k];
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double tot[2] = {0.0, 0.0};
+  for (int k = 0; k < 2; ++k)
+    for (unsigned w = 0; w < blockDim.x / 64; ++w) tot[k] += red[k][w];
+  rms[0] = tot[1] > 0.0 ? sqrt(tot[0] / tot[1]) : 0.0;
+}
+
+}  // namespace
+
+extern "C" mfmg_status mfmg_divergence_rms_noalloc(mfmg_hierarchy *h, const double *div,
+                                                   double *rms, void *stream) {
+  if (!h || !div || !rms) return fail(MFMG_ERR_INVALID_ARG, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  double *parts = nullptr;
+  hipError_t e = scratch_address(&parts);
+  if (e != hipSuccess)
+    return fail(MFMG_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  PcgArgs P = pcg_args(h);
+  unsigned G = grid_reduce(h->co->dt->nlb);
+  if (int64_t(G) > kMaxReduceBlocks)
+    return fail(MFMG_ERR_INVALID_ARG, "reduction grid larger than the fixed partial-sum array");
+  for (int what = 0; what < 2; ++what) {
+    P.partials = parts + what * kMaxReduceBlocks;
+    hipLaunchKernelGGL(k_div_rms_part, dim3(G), dim3(kBlock), 0, s, P, div, what);
+  }
+  hipLaunchKernelGGL(k_rms_finish, dim3(1), dim3(1024), 0, s, (const double *)parts,
+                     int64_t(G), rms);
+  e = hipGetLastError();
+  if (e != hipSuccess) return fail(MFMG_ERR_HIP, hipGetErrorString(e));
   return MFMG_OK;
 }

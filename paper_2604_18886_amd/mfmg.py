@@ -102,6 +102,7 @@ SIGNATURES = {
     "mfmg_divergence": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "mfmg_project_velocity": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "mfmg_divergence_rms": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(ctypes.c_double), _VP]),
+    "mfmg_divergence_rms_noalloc": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "mfmg_apply_operator": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int, _VP]),
     "mfmg_apply_precond": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int, _VP]),
     "mfmg_profile": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP,
@@ -398,6 +399,17 @@ def divergence_rms(h, div):
     _check(_lib.mfmg_divergence_rms(h._h, _vec(div, h.n_leaves, "div"), ctypes.byref(r),
                                     _stream()))
     return r.value
+
+
+def divergence_rms_noalloc(h, div, out=None):
+    """mfmg_divergence_rms_noalloc: the RMS into a device tensor of one
+    double (out, allocated here when None), queued on the current stream."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=div.device)
+    _check(_lib.mfmg_divergence_rms_noalloc(h._h, _vec(div, h.n_leaves, "div"),
+                                            _vec(out, 1, "out"), _stream()))
+    return out
 
 
 def project(h, beta, u, rtol=1e-10, max_iter=200):
