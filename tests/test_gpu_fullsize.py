@@ -212,3 +212,81 @@ def test_offset_limit_and_largest_mixed_solve():
     print(f"  mixed: {st['iters']} iterations, true residual {st['rel_resid_true']:.2e}, "
           f"{st['seconds'] * 1e3:.1f} ms", flush=True)
     assert st["status"] == 0 and st["rel_resid_true"] <= 1e-10
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_full_adjoint_gradient_against_finite_differences(precision):
+    """The adjoint workload's full octree (levels 6..9, 2.3M leaves): the
+    GPU's dL/dbeta on 50 seeded faces (25 T-junction or cut faces, 25 from
+    all faces with both sides active) against central finite differences
+    of the GPU's own forward solves, eps = 1e-6 relative to the face's
+    cells' coupling, each side a difference solve (the oracle's
+    finite-difference rule, reading 17):
+        A(beta +- eps e_f) dp = -+ eps (dA/dbeta_f) p,
+    with the perturbed coefficients assembled and coarsened on the device
+    and (dA/dbeta_f) p formed from a unit step (A is linear in beta).  The
+    base residual r0 = rhs - A p (1e-11 of rhs) is left out of the
+    right-hand side: the difference is then taken at A^-1 (A p), which
+    differs from A^-1 rhs by the solve's residual, and each dp is a solve
+    to its own tolerance.  The
+    gradient itself is compared with the oracle's at this size by
+    test_full_adjoint_matches_oracle, and the oracle's gradient with its own
+    finite differences on smaller members of the family."""
+    import torch
+    from oracle import discretize as D
+    from paper_2604_18886_amd import mfmg
+    case = _case(3)
+    d = case.disc
+    dev = case.device
+    act = d.active
+    both = act[d.face_owner] & ((d.face_other < 0) | act[np.maximum(d.face_other, 0)])
+    special = np.nonzero(((d.face_kind == D.COARSE) | (case.beta < 1)) & both)[0]
+    faces = problems.sample_faces(d.n_faces, special, count=50, pool=np.nonzero(both)[0])
+    assert len(faces) == 50 and np.all(both[faces])
+
+    def hierarchy(beta):
+        co = mfmg.assemble_coeffs(case.tree, dev(beta), case.bc, case.theta)
+        return mfmg.build_hierarchy(co, coarsest_level=3, precision=precision)
+
+    h0 = hierarchy(case.beta)
+    rhs_d = dev(case.rhs)
+    p_d, _ = mfmg.pcg_solve(h0, rhs_d, rtol=1e-11)
+    p = p_d.cpu().numpy()
+    pt = problems.adjoint_target(case.T.level, case.T.ijk, np.abs(p).max())
+    e = np.where(act, p - pt, 0.0)
+    _, grad_d, st = mfmg.pcg_solve_adjoint(h0, p_d, dev(2.0 * e), rtol=1e-11)
+    assert st["status"] == 0
+    grad = grad_d.cpu().numpy()
+    act_d = torch.as_tensor(act, device="cuda")
+    Ap0 = mfmg.apply_operator(h0, p_d)
+    scale = d.face_scale()
+    fd = np.zeros(len(faces))
+    e_d = dev(e)
+    for n, f in enumerate(faces):
+        # step relative to the coupling of the face's cells (reading 17)
+        cells = [d.face_owner[f]] + ([d.face_other[f]] if d.face_other[f] >= 0 else [])
+        dc = [scale[f]] + ([scale[f] / 2.0 if d.face_kind[f] == D.COARSE else scale[f]]
+                           if d.face_other[f] >= 0 else [])
+        step = 1e-6 * min([1.0] + [d.c[i] / x for i, x in zip(cells, dc) if x > 0])
+        bu = case.beta.copy()
+        bu[f] += 1.0
+        hu = hierarchy(bu)
+        dAp = mfmg.apply_operator(hu, p_d) - Ap0
+        del hu
+        dls = []
+        for sgn in (1.0, -1.0):
+            bb = case.beta.copy()
+            bb[f] += sgn * step
+            hs = hierarchy(bb)
+            b = torch.where(act_d, -sgn * step * dAp, 0.0)
+            dp, sst = mfmg.pcg_solve(hs, b, rtol=1e-12)
+            assert sst["status"] in (0, 1) and sst["rel_resid_true"] <= 1e-11
+            del hs
+            dls.append(float(2.0 * torch.dot(e_d, dp) + torch.dot(dp, dp)))
+        fd[n] = (dls[0] - dls[1]) / (2.0 * step)
+    ga = grad[faces]
+    denom = np.maximum(np.abs(fd), 1e-8 * np.abs(fd).max())
+    err = np.max(np.abs(ga - fd) / denom)
+    print(f"  precision={precision}: FD check on {len(faces)} faces of the full octree: "
+          f"max rel err {err:.2e}", flush=True)
+    assert err <= 1e-6
