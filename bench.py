@@ -52,9 +52,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(precision_name, level):
-    """HBM bytes per launch of the dominant kernel from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel source."""
+def measured_traffic(precision_name, level, key="hbm_bytes_per_launch"):
+    """HBM bytes per launch of the dominant kernel (or, with key, per whole
+    cycle) from the committed rocprofv3 counter summary, if it was taken on
+    the current kernel source."""
     path = os.path.join(ROOT, "profiles", "traffic_smooth_large_workload.json")
     if not os.path.exists(path):
         return None
@@ -63,7 +64,44 @@ def measured_traffic(precision_name, level):
     rec = t.get(precision_name)
     if not rec or rec.get("source_hash") != kernel_source_hash() or rec.get("level") != level:
         return None
-    return rec["hbm_bytes_per_launch"]
+    return rec.get(key)
+
+
+def traced_launch_us(kernel):
+    """Average duration (us) of a kernel in the committed rocprofv3 kernel
+    statistics of the benchmark, if taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "kernel_trace_large_workload.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("source_hash") != kernel_source_hash():
+        return None
+    rec = t.get("kernels", {}).get(kernel)
+    return rec["avg_us"] if rec else None
+
+
+def summarize_trace(stats_csv):
+    """Per-kernel calls and average duration from a rocprofv3 --stats
+    kernel_stats.csv, stored with the kernel source hash."""
+    import csv
+    kernels = {}
+    with open(stats_csv) as fh:
+        for r in csv.DictReader(fh):
+            # "void mfmg::k_smooth<float, float, __half, 2>(mfmg::LevelArgs<...>, int)"
+            # -> "mfmg::k_smooth<float, float, __half, 2>"
+            name = r["Name"].strip()
+            if name.startswith("void "):
+                name = name[5:]
+            name = name.split("(", 1)[0]
+            kernels[name] = {"calls": int(r["Calls"]),
+                             "avg_us": float(r["AverageNs"]) / 1e3,
+                             "total_ms": float(r["TotalDurationNs"]) / 1e6}
+    rec = {"source_hash": kernel_source_hash(), "kernels": kernels}
+    path = os.path.join(ROOT, "profiles", "kernel_trace_large_workload.json")
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    return rec
 
 
 COPY_BYTES = 1 << 30      # plain copy used to scale the counters
@@ -80,11 +118,18 @@ def smooth_precision(kernel_name):
     return None
 
 
+CYCLE_KERNELS = ("k_fill", "k_smooth", "k_restrict", "k_fas_rhs", "k_bottom", "k_prolong",
+                 "k_coarsest")
+
+
 def summarize_pmc(fetch_csv, write_csv, level):
     """HBM bytes per launch of the finest half-sweep (mixed or FP64, from the
-    kernel name) from two rocprofv3 counter_collection.csv files (FETCH_SIZE,
-    WRITE_SIZE in KiB per dispatch), each scaled by what the same counter
-    reads for a plain copy of COPY_BYTES bytes.  Returns (precision, record)."""
+    kernel name) and per whole cycle, from two rocprofv3 counter_collection.csv
+    files (FETCH_SIZE, WRITE_SIZE in KiB per dispatch) of a --traffic-pass
+    run, each scaled by what the same counter reads for a plain copy of
+    COPY_BYTES bytes.  The half-sweeps are the k_smooth dispatches before the
+    first cycle's k_fill; the cycles are every cycle kernel after it, per
+    k_bottom dispatch (one per V-cycle).  Returns (precision, record)."""
     import csv
 
     def dispatches(path, counter):
@@ -104,21 +149,28 @@ def summarize_pmc(fetch_csv, write_csv, level):
     precisions = set()
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         rows = dispatches(path, counter)
-        smooth = [v for _, n, v in rows if "k_smooth" in n]
-        precisions |= {smooth_precision(n) for _, n, _ in rows if "k_smooth" in n}
-        last = max((d for d, n, _ in rows if "k_smooth" in n), default=None)
+        first_fill = min((d for d, n, _ in rows if "k_fill" in n), default=None)
+        smooth = [v for d, n, v in rows if "k_smooth<" in n
+                  and (first_fill is None or d < first_fill)]
+        precisions |= {smooth_precision(n) for _, n, _ in rows if "k_smooth<" in n}
+        cyc = [(d, n, v) for d, n, v in rows if first_fill is not None and d >= first_fill
+               and any(k in n for k in CYCLE_KERNELS)]
+        ncyc = sum(1 for _, n, _ in cyc if "k_bottom" in n)
+        last = max((d for d, n, _ in rows if any(k in n for k in CYCLE_KERNELS)), default=None)
         # the TRAFFIC_REPS device copies of COPY_BYTES that follow the
-        # half-sweeps (earlier copy dispatches move other, smaller buffers)
+        # half-sweeps and cycles (earlier copy dispatches move other buffers)
         copy = [v for d, n, v in rows
                 if last is not None and d > last and "copy" in n.lower()]
-        if not smooth or len(copy) != TRAFFIC_REPS:
-            raise SystemExit(f"{path}: expected k_smooth dispatches followed by "
+        if not smooth or len(copy) != TRAFFIC_REPS or not ncyc:
+            raise SystemExit(f"{path}: expected k_smooth dispatches, cycles and "
                              f"{TRAFFIC_REPS} copies for {counter}")
         factor = (sum(copy) / len(copy)) / COPY_BYTES
         out[counter] = {"per_launch_bytes_raw": sum(smooth) / len(smooth),
                         "launches": len(smooth), "copy_raw_bytes": sum(copy) / len(copy),
                         "copy_factor": factor,
-                        "per_launch_bytes": sum(smooth) / len(smooth) / factor}
+                        "per_launch_bytes": sum(smooth) / len(smooth) / factor,
+                        "cycles": ncyc,
+                        "per_cycle_bytes": sum(v for _, _, v in cyc) / ncyc / factor}
     if len(precisions) != 1 or None in precisions:
         raise SystemExit("expected the half-sweeps of one hierarchy, found "
                          f"{sorted(map(str, precisions))}")
@@ -127,6 +179,10 @@ def summarize_pmc(fetch_csv, write_csv, level):
            "write_bytes_per_launch": out["WRITE_SIZE"]["per_launch_bytes"],
            "hbm_bytes_per_launch": (out["FETCH_SIZE"]["per_launch_bytes"]
                                     + out["WRITE_SIZE"]["per_launch_bytes"]),
+           "cycle_fetch_bytes": out["FETCH_SIZE"]["per_cycle_bytes"],
+           "cycle_write_bytes": out["WRITE_SIZE"]["per_cycle_bytes"],
+           "cycle_hbm_bytes": (out["FETCH_SIZE"]["per_cycle_bytes"]
+                               + out["WRITE_SIZE"]["per_cycle_bytes"]),
            "counters": out}
     return precisions.pop(), rec
 
@@ -414,7 +470,13 @@ def main():
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--projection-study", action="store_true",
                     help="only the static projection test over root cell sizes (one JSON line)")
+    ap.add_argument("--summarize-trace", metavar="KERNEL_STATS_CSV",
+                    help="store per-kernel averages of a rocprofv3 --stats run of bench.py")
     args = ap.parse_args()
+    if args.summarize_trace:
+        rec = summarize_trace(args.summarize_trace)
+        print(json.dumps({"kernels": len(rec["kernels"]), "source_hash": rec["source_hash"]}))
+        return
     if args.summarize_pmc:
         spec = __import__("problems").config_spec(args.workload)
         prec, rec = summarize_pmc(*args.summarize_pmc, spec["max_level"])
@@ -474,13 +536,15 @@ def main():
     if args.traffic_pass:
         h = mfmg.build_hierarchy(co, precision=mfmg.FP64 if args.traffic_fp64 else mfmg.MIXED)
         ms, by = mfmg.profile(h, mfmg.PROFILE_SMOOTH, L, reps=TRAFFIC_REPS)
+        mfmg.profile(h, mfmg.PROFILE_CYCLE, 0, reps=TRAFFIC_REPS)
         src = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
         for _ in range(TRAFFIC_REPS):
             dst.copy_(src)
         torch.cuda.synchronize()
-        log(f"[bench] traffic pass: {TRAFFIC_REPS} half-sweeps at level {L} "
-            f"({by:.3e} algorithmic bytes each), {TRAFFIC_REPS} copies of {COPY_BYTES} bytes")
+        log(f"[bench] traffic pass: {TRAFFIC_REPS + 1} half-sweeps at level {L} "
+            f"({by:.3e} algorithmic bytes each), {TRAFFIC_REPS + 1} cycles, "
+            f"{TRAFFIC_REPS} copies of {COPY_BYTES} bytes")
         return
     hiers = {"mixed": mfmg.build_hierarchy(co, precision=mfmg.MIXED),
              "fp64": mfmg.build_hierarchy(co, precision=mfmg.FP64)}
@@ -570,6 +634,7 @@ def main():
             "kernel": f"k_smooth<float,float,__half> colour half-sweep, level {L}",
             "algorithmic_bytes_per_launch": head["smooth_bytes"],
             "avg_launch_us": head["smooth_ms"] * 1e3,
+            "rocprof_avg_launch_us": traced_launch_us("mfmg::k_smooth<float, float, __half, 2>"),
             "stream_copy_gbs": head["copy_gbs"],
             "frac_of_stream_copy": head["smooth_gbs"] / head["copy_gbs"]}
     cpu = None
@@ -607,6 +672,8 @@ def main():
                  "iters": out["fp64"]["iters"], "rel_resid_true": out["fp64"]["rel_resid_true"],
                  "vcycle_gbs": out["fp64"]["cycle_gbs"], "vcycle_ms": out["fp64"]["cycle_ms"],
                  "vcycle_frac_of_peak": out["fp64"]["cycle_gbs"] / HBM_PEAK_GBS,
+                 "vcycle_algorithmic_bytes": out["fp64"]["cycle_bytes"],
+                 "vcycle_traffic": measured_traffic("fp64", L, "cycle_hbm_bytes"),
                  "smooth_us": out["fp64"]["smooth_ms"] * 1e3,
                  "smooth_algorithmic_bytes": out["fp64"]["smooth_bytes"],
                  "smooth_frac_of_peak": out["fp64"]["smooth_gbs"] / HBM_PEAK_GBS,
@@ -617,6 +684,8 @@ def main():
                   "rel_l2_diff_vs_fp64": mixed_vs_fp64,
                   "vcycle_gbs": head["cycle_gbs"], "vcycle_ms": head["cycle_ms"],
                   "vcycle_frac_of_peak": head["cycle_gbs"] / HBM_PEAK_GBS,
+                  "vcycle_algorithmic_bytes": head["cycle_bytes"],
+                  "vcycle_traffic": measured_traffic("mixed", L, "cycle_hbm_bytes"),
                   "adjoint_ms": head["adjoint_ms"], "adjoint_iters": head["adjoint_iters"],
                   "wcycle_ms_per_solve": dt_w * 1e3, "wcycle_iters": stw["iters"]},
         "rebuild": rebuild,

@@ -31,13 +31,32 @@ def write_counters(path, counter, rows):
                             "Counter_Value": v})
 
 
+def cycle_kernels(smooth_name):
+    """Kernel names of one V-cycle's dispatches (a short one) and the KiB of
+    each: fill, two half-sweeps, restriction, bottom, prolongation, two
+    half-sweeps."""
+    t = smooth_name.replace("k_smooth<", "{}<")
+    return [("void mfmg::k_fill<float>(float*, long, float)", 10.0),
+            (smooth_name, 100.0), (smooth_name, 100.0),
+            (t.format("k_restrict"), 50.0), (t.format("k_bottom"), 5.0),
+            (t.format("k_prolong"), 20.0), (smooth_name, 100.0), (smooth_name, 100.0)]
+
+
+CYCLE_KIB = 485.0
+
+
 def counter_run(tmp_path, counter, smooth_name, smooth_kib, copy_kib, copies=4, tag=""):
     """One counter pass as the traffic pass lays it out: a small copy, five
-    half-sweeps (each reported as two counter instances), then the 1 GiB
-    copies that scale the counter."""
+    half-sweeps (each reported as two counter instances), five cycles, then
+    the 1 GiB copies that scale the counter."""
     rows = [(1, COPY, [64.0])]
     rows += [(2 + i, smooth_name, [smooth_kib / 2, smooth_kib / 2]) for i in range(5)]
-    rows += [(7 + i, COPY, [copy_kib]) for i in range(copies)]
+    d = 7
+    for _ in range(5):
+        for name, kib in cycle_kernels(smooth_name):
+            rows.append((d, name, [kib]))
+            d += 1
+    rows += [(d + i, COPY, [copy_kib]) for i in range(copies)]
     path = os.path.join(tmp_path, f"{counter}{tag}.csv")
     write_counters(path, counter, rows)
     return path
@@ -55,6 +74,10 @@ def test_summary_scales_each_counter_by_its_copy_reading(tmp_path):
     assert rec["fetch_bytes_per_launch"] == pytest.approx(3000.0 * KIB / 0.5)
     assert rec["write_bytes_per_launch"] == pytest.approx(500.0 * KIB)
     assert rec["hbm_bytes_per_launch"] == pytest.approx(6000.0 * KIB + 500.0 * KIB)
+    # the cycles: every cycle kernel after the first fill, per bottom dispatch
+    assert rec["counters"]["FETCH_SIZE"]["cycles"] == 5
+    assert rec["cycle_fetch_bytes"] == pytest.approx(CYCLE_KIB * KIB / 0.5)
+    assert rec["cycle_hbm_bytes"] == pytest.approx(CYCLE_KIB * KIB / 0.5 + CYCLE_KIB * KIB)
 
 
 def test_summary_names_the_fp64_hierarchy(tmp_path):
@@ -101,6 +124,25 @@ def test_committed_traffic_records_are_consistent():
         for c in rec["counters"].values():
             assert c["per_launch_bytes"] == pytest.approx(
                 c["per_launch_bytes_raw"] / c["copy_factor"])
+
+
+def test_trace_summary_keeps_kernel_averages_with_the_source(tmp_path, monkeypatch):
+    os.makedirs(os.path.join(tmp_path, "profiles"))
+    stats = os.path.join(tmp_path, "kernel_stats.csv")
+    with open(stats, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Name", "Calls", "TotalDurationNs", "AverageNs",
+                                           "Percentage", "MinNs", "MaxNs", "StdDev"])
+        w.writeheader()
+        w.writerow({"Name": MIXED, "Calls": 4,
+                    "TotalDurationNs": 440000, "AverageNs": 110000.0, "Percentage": 50,
+                    "MinNs": 100000, "MaxNs": 120000, "StdDev": 1})
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "h-current")
+    bench.summarize_trace(stats)
+    assert bench.traced_launch_us("mfmg::k_smooth<float, float, __half, 2>") == 110.0
+    assert bench.traced_launch_us("mfmg::k_restrict<float, float, __half, 2>") is None
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "h-edited")
+    assert bench.traced_launch_us("mfmg::k_smooth<float, float, __half, 2>") is None
 
 
 def test_more_than_one_gpu_is_refused_with_a_message():
