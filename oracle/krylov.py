@@ -136,7 +136,7 @@ def solve_and_grad(disc, hier, rhs, loss_grad, rtol=1e-10, max_iter=200):
 
 
 def fd_gradient(disc_factory, beta, p, p_target, faces, eps=1e-6, rtol=1e-13,
-                precond_factory=None, max_iter=400, rhs=None):
+                precond_factory=None, max_iter=400, rhs=None, return_steps=False):
     """Central finite differences of L = sum_active (p - p_t)^2 with respect to
     beta_f, computed as difference solves so that cancellation does not
     destroy the O(eps) change of L:
@@ -158,8 +158,10 @@ def fd_gradient(disc_factory, beta, p, p_target, faces, eps=1e-6, rtol=1e-13,
     cell (all face fractions ~1e-4) a fixed step of 1e-6 would change its
     operator by ~1% and the O(eps^2) error of the central difference would
     dominate; elsewhere c_i / (dc_i/dbeta_f) is the sum of the cell's face
-    betas (about 6) and eps_f = eps.  Returns g_f."""
+    betas (about 6) and eps_f = eps.  Returns g_f (and the steps eps_f with
+    return_steps)."""
     out = np.zeros(len(faces))
+    steps = np.zeros(len(faces))
     base = disc_factory(beta)
     base_Ap = base.A @ p
     r0 = np.zeros_like(p) if rhs is None else np.where(base.active, rhs - base_Ap, 0.0)
@@ -171,6 +173,7 @@ def fd_gradient(disc_factory, beta, p, p_target, faces, eps=1e-6, rtol=1e-13,
         cells = [base.face_owner[f]] + ([base.face_other[f]] if base.face_other[f] >= 0 else [])
         ratio = [base.c[i] / (du.c[i] - base.c[i]) for i in cells if du.c[i] != base.c[i]]
         step = eps * min([1.0] + ratio)
+        steps[n] = step
         dls = []
         for sgn in (+1.0, -1.0):
             bb = beta.copy()
@@ -184,4 +187,4 @@ def fd_gradient(disc_factory, beta, p, p_target, faces, eps=1e-6, rtol=1e-13,
             e = np.where(act, p - p_target, 0.0)
             dls.append(2.0 * e @ dp + dp @ dp)
         out[n] = (dls[0] - dls[1]) / (2.0 * step)
-    return out
+    return (out, steps) if return_steps else out

@@ -60,15 +60,20 @@ def test_adjoint_gradient_matches_difference_solve_fd():
     special = np.nonzero((d.face_kind == D.COARSE) | (beta < 1))[0]
     both = d.active[d.face_owner] & ((d.face_other < 0) | d.active[np.maximum(d.face_other, 0)])
     special = np.intersect1d(special, np.nonzero(both)[0])
-    faces = problems.sample_faces(d.n_faces, special, count=20)
-    faces = faces[both[faces]]
+    faces = problems.sample_faces(d.n_faces, special, count=20, pool=np.nonzero(both)[0])
+    assert len(faces) == 20 and np.all(both[faces])
 
     def factory(bb):
         dd = D.Discretization(T, None, bc, th)
         dd.set_beta(bb)
         return dd
-    fd = K.fd_gradient(factory, beta, p, pt, faces, eps=1e-6, rtol=1e-13,
-                       precond_factory=lambda dd: hierarchy(dd).vcycle, rhs=rhs)
+    fd, steps = K.fd_gradient(factory, beta, p, pt, faces, eps=1e-6, rtol=1e-13,
+                              precond_factory=lambda dd: hierarchy(dd).vcycle, rhs=rhs,
+                              return_steps=True)
     ga = g[faces]
     denom = np.maximum(np.abs(fd), 1e-8 * np.abs(fd).max())
-    assert np.max(np.abs(ga - fd) / denom) <= 1e-6
+    err = np.max(np.abs(ga - fd) / denom)
+    reduced = int((steps < 1e-6).sum())
+    print(f"  FD on {len(faces)} faces: max rel err {err:.2e}; {reduced} faces took a step "
+          f"below 1e-6 (smallest {steps.min():.2e})")
+    assert err <= 1e-6
