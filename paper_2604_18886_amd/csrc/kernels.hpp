@@ -434,13 +434,17 @@ __device__ __forceinline__ LaneC<V, CL> lane_consts() {
 struct WaveLoop {
   uint32_t first, end, step;
 };
-__device__ __forceinline__ WaveLoop wave_loop(uint32_t n) {
-  uint32_t x = blockIdx.x & 7u;
-  uint32_t j = (blockIdx.x >> 3) * kWavesPerBlock + wave_id();
+// The loop of workgroup `block` of a grid of `blocks` (a multiple of 8).
+__device__ __forceinline__ WaveLoop wave_loop_of(uint32_t n, uint32_t block, uint32_t blocks) {
+  uint32_t x = block & 7u;
+  uint32_t j = (block >> 3) * kWavesPerBlock + wave_id();
   uint32_t chunk = (n + 7u) >> 3;
   uint32_t lo = x * chunk;
   uint32_t hi = lo + chunk < n ? lo + chunk : n;
-  return {lo + j, hi, (gridDim.x >> 3) * kWavesPerBlock};
+  return {lo + j, hi, (blocks >> 3) * kWavesPerBlock};
+}
+__device__ __forceinline__ WaveLoop wave_loop(uint32_t n) {
+  return wave_loop_of(n, blockIdx.x, gridDim.x);
 }
 
 // CP: cache policy of the loads whose data a launch uses once (coefficient
@@ -1256,7 +1260,7 @@ __device__ __forceinline__ LevelViewT<V, CL, CI, CP> level_view_T(const LevelArg
 // entry):
 //   (c_m - sum_{T faces of m} k) w_m - sum_{other faces} k W_nbr
 //   + (1 / n_active siblings) sum over the sibling group's T-faces (k_i/2) w_i
-// (the coupling to the coarser level, B^T, is applied by k_T_coupling).  The
+// (the coupling to the coarser level, B^T, is applied by coupling_brick).  The
 // loads across T-faces are out of range, so those faces drop out of the
 // neighbour sum by themselves.
 template <bool INNER, class V, class CL, class CI, int CP>
@@ -1367,17 +1371,12 @@ __global__ void __launch_bounds__(kBlock) k_T_apply(LevelArgsT<V, CL, CI> A, int
 }
 
 // Coupling of level l to the coarser leaves, transposed: on the leaf bricks
-// of level l-1 that have an inner neighbour (list[0, n)), RHO_J += sum over
-// the fine T-face cells f next to J of (k_f / 2) W_f (the fine cells are
-// children of J's inner neighbour).
+// of level l-1 that have an inner neighbour (a list), RHO_J += sum over the
+// fine T-face cells f next to J of (k_f / 2) W_f (the fine cells are
+// children of J's inner neighbour); this is one listed brick b (lane m).
 template <class V, class CL, class CI>
-__global__ void __launch_bounds__(kBlock) k_T_coupling(LevelArgsT<V, CL, CI> A,
-                                                       const uint32_t *list, uint32_t n) {
-  if (A.done && *A.done) return;
-  uint32_t i = blockIdx.x * kWavesPerBlock + wave_id();
-  int m = threadIdx.x & (kWave - 1);
-  if (i >= n) return;
-  uint32_t b = list[i];
+__device__ __forceinline__ void coupling_brick(const LevelArgsT<V, CL, CI> &A, uint32_t b,
+                                               int m) {
   const BrickMeta M = A.T.meta[b];
   if (!(M.flags & kFlagInner)) return;
   if (!((act_mask(M) >> m) & 1ull)) return;
@@ -1398,6 +1397,32 @@ __global__ void __launch_bounds__(kBlock) k_T_coupling(LevelArgsT<V, CL, CI> A,
     }
   }
   A.RHO[b * 64u + m] += acc;
+}
+
+// A transposed half-sweep's apply step on level l (workgroups [0, g_apply),
+// as k_T_apply) and, in the same launch, the coupling of its w to the
+// coarser leaves (the workgroups after, one wave per listed brick): the coupling reads
+// only w, which the apply step does not write, and writes the residual of
+// level l-1 leaf bricks, which the apply step does not touch.
+template <class V, class CL, class CI, int CP = kCpolDefault>
+__global__ void __launch_bounds__(kBlock) k_T_apply_couple(LevelArgsT<V, CL, CI> A, int colour,
+                                                           int next, LevelArgsT<V, CL, CI> C,
+                                                           const uint32_t *list, uint32_t n,
+                                                           uint32_t g_apply) {
+  if (A.done && *A.done) return;
+  if (blockIdx.x < g_apply) {
+    const LaneC<V, CL> L = lane_consts<V, CL>();
+    const LevelViewT<V, CL, CI, CP> X = level_view_T<CP>(A);
+    const WaveLoop W = wave_loop_of(A.R.n(), blockIdx.x, g_apply);
+    for (uint32_t i = W.first; i < W.end; i += W.step) {
+      if (i < A.R.n_leaf) apply_T_brick<false>(X, L, A.R.leaf_lo + i, colour, next);
+      else apply_T_brick<true>(X, L, A.R.inner_lo + (i - A.R.n_leaf), colour, next);
+    }
+  } else {
+    uint32_t i = (blockIdx.x - g_apply) * kWavesPerBlock + wave_id();
+    int m = threadIdx.x & (kWave - 1);
+    if (i < n) coupling_brick(C, list[i], m);
+  }
 }
 
 // Transposed prolongation input: the children's residual sums move to the

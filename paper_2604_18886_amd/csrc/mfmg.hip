@@ -1219,20 +1219,28 @@ struct CycleT {
     auto A = args(l, 0);
     A.W = win;
     A.W2 = wout ? wout : win;
+    uint32_t nc = l > h->lc ? h->couple_n[size_t(l - 1)] : 0;
+    if (nc) {
+      // the apply step and the coupling in one launch
+      auto C = args(l - 1, 1);
+      C.W = win;
+      const uint32_t *list = (const uint32_t *)h->couple.p + h->couple_lo[size_t(l - 1)];
+      unsigned ga = stencil_grid_T<V>(A.R.n());
+      dim3 g(ga + grid_for(nc));
+      if (h->stream_lv[size_t(l)])
+        hipLaunchKernelGGL((k_T_apply_couple<V, CL, CI, kCpolStream>), g, dim3(kBlock), 0, s, A,
+                           colour, next, C, list, nc, ga);
+      else
+        hipLaunchKernelGGL((k_T_apply_couple<V, CL, CI>), g, dim3(kBlock), 0, s, A, colour,
+                           next, C, list, nc, ga);
+      return;
+    }
     if (h->stream_lv[size_t(l)])
       hipLaunchKernelGGL((k_T_apply<V, CL, CI, kCpolStream>), dim3(stencil_grid_T<V>(A.R.n())),
                          dim3(kBlock), 0, s, A, colour, next);
     else
       hipLaunchKernelGGL((k_T_apply<V, CL, CI>), dim3(stencil_grid_T<V>(A.R.n())), dim3(kBlock),
                          0, s, A, colour, next);
-    if (l > h->lc) {
-      auto C = args(l - 1, 1);
-      C.W = win;
-      uint32_t n = h->couple_n[size_t(l - 1)];
-      if (n)
-        hipLaunchKernelGGL((k_T_coupling<V, CL, CI>), dim3(grid_for(n)), dim3(kBlock), 0, s, C,
-                           (const uint32_t *)h->couple.p + h->couple_lo[size_t(l - 1)], n);
-    }
   }
   // Transpose of smooth(l, (c0, 1 - c0), nu): 2 nu half-sweeps with the
   // colours in reversed order.  Each apply step also forms the w of the
