@@ -86,9 +86,10 @@ def test_one_cycle_mixed_against_stored_precision_oracle(case):
     """The mixed cycle (FP32 values, FP32 leaf / FP16 inner coefficients)
     against the oracle's FP64 cycle on the coefficients that store keeps
     (Hierarchy.stored_precision): what is left is FP32 arithmetic (and the
-    FP32 rounding of the input), about 1e-6 relative.  The coefficient
-    rounding alone moves the cycle by far more on the jittered families,
-    so a defect in the FP32/FP16 kernels larger than FP32 rounding fails."""
+    FP32 rounding of the input), measured 6e-8 to 7e-7 relative.  The
+    coefficient rounding alone moves the cycle by 6e-7 (cut sphere) to
+    1.4e-5 (cut box) on the jittered families, and by nothing where beta = 1
+    (dyadic coefficients are stored exactly)."""
     from paper_2604_18886_amd import mfmg
     h = case.gpu_hierarchy(precision=mfmg.MIXED)
     rng = np.random.default_rng(9)
