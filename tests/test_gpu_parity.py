@@ -150,6 +150,30 @@ def test_null_space_all_neumann():
     assert rel(p, x) <= 1e-9
 
 
+def test_mixed_w_cycle_against_stored_precision_oracle():
+    """The mixed-precision W-cycle (mu = 2) against the oracle's W-cycle on
+    the coefficients the mixed store keeps, and its solve against the FP64
+    oracle's solution."""
+    import problems
+    from gpu_fixtures import Case
+    from oracle import krylov as K
+    from oracle import multigrid as M
+    from paper_2604_18886_amd import mfmg
+    case = Case(3, problems.config_spec(3, 5, 7))
+    H = M.Hierarchy(case.disc, coarsest=3, mu=2)
+    h = case.gpu_hierarchy(mu=2, precision=mfmg.MIXED)
+    rng = np.random.default_rng(11)
+    r = np.where(case.disc.active, rng.uniform(-1, 1, case.T.n), 0.0)
+    z = mfmg.apply_precond(h, case.device(r)).cpu().numpy()
+    err = rel(z, H.stored_precision().vcycle(r))
+    p, st = mfmg.pcg_solve(h, case.device(case.rhs), rtol=1e-10)
+    x, _ = K.pcg(case.disc.A, case.rhs, H.vcycle, 1e-13, 400, active=case.disc.active)
+    print(f"  mixed W-cycle vs stored-precision oracle {err:.2e}; solve iters {st['iters']} "
+          f"err {rel(p.cpu().numpy(), x):.2e}", flush=True)
+    assert err <= 1e-5
+    assert st["status"] == 0 and rel(p.cpu().numpy(), x) <= 1e-9
+
+
 @pytest.mark.parametrize("mu", [2])
 def test_w_cycle_matches_oracle(mu):
     """The mu-cycle (Algorithm 4 with mu recursive coarse solves; mu = 2 is
