@@ -36,11 +36,22 @@ constexpr uint32_t kFlagT = 0x3fu;
 constexpr uint32_t kFlagInner = 0x3fu << 8;
 constexpr uint32_t kFlagWall = 0x3fu << 16;
 
+// Per brick: for each axis a, the parent brick's same-level neighbour on the
+// brick's side of the parent along a (the parent's nbr[2 a + bit a of the
+// brick's octant]); -1 where there is none or the brick has no parent.  The
+// brick across face d of axis a has that brick as its parent when the face
+// lies on the parent's face, and the brick's own parent otherwise.
+struct alignas(16) ParentNbrs {
+  int32_t across[3];
+  int32_t pad;
+};
+
 struct Topo {
   uint32_t nlb;            // leaf bricks (device ids 0 .. nlb-1)
   uint32_t nb;             // all bricks
   const BrickMeta *meta;   // nb records
   const int32_t *child;    // 8 per brick (octant dx + 2 dy + 4 dz), -1 for leaves
+  const ParentNbrs *pnb;   // nb entries (hierarchies only; null elsewhere)
 };
 
 // Bricks of one level: a leaf range followed by an inner range.
@@ -60,6 +71,14 @@ __device__ __forceinline__ BrickMeta load_meta(const BrickMeta *meta, uint32_t b
   return ((const __attribute__((address_space(4))) BrickMeta *)meta)[b];
 #else
   return meta[b];  // host pass: never executed
+#endif
+}
+
+__device__ __forceinline__ ParentNbrs load_parent_nbrs(const ParentNbrs *pnb, uint32_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return ((const __attribute__((address_space(4))) ParentNbrs *)pnb)[b];
+#else
+  return pnb[b];  // host pass: never executed
 #endif
 }
 
@@ -208,6 +227,23 @@ __global__ void __launch_bounds__(kBlock) k_active_mask(const double *coef, uint
     meta[b].act[0] = uint32_t(mask);
     meta[b].act[1] = uint32_t(mask >> 32);
   }
+}
+
+// The parent-neighbour table (ParentNbrs), one thread per brick.
+__global__ void __launch_bounds__(kBlock) k_parent_nbrs(Topo T, ParentNbrs *out) {
+  uint32_t b = blockIdx.x * kBlock + threadIdx.x;
+  if (b >= T.nb) return;
+  const BrickMeta &M = T.meta[b];
+  ParentNbrs r;
+  r.pad = 0;
+  for (int a = 0; a < 3; ++a) {
+    r.across[a] = -1;
+    if (M.parent >= 0) {
+      int side = (octant_of(M) >> a) & 1;
+      r.across[a] = T.meta[M.parent].nbr[2 * a + side];
+    }
+  }
+  out[b] = r;
 }
 
 // Algorithm 3: coarse coefficients of the inner bricks [lo, lo + n) from
@@ -371,6 +407,8 @@ struct LaneC {
   uint32_t poff[6];  // out[d] ? p * sizeof(V) : kOutOfRange
   uint32_t foff[3];  // plus-face slot of the cell on axis a, in bytes
   int colour;        // (x + y + z) & 1
+  int esrc[6];       // fused prolongation: lane holding the correction of the
+                     // parent of the neighbour across d (prolong_gather)
   // FP64 only: gathered face loads of the full stencil (see stencil_sum)
   uint32_t goff[2];  // lane k < 48 of gather h: byte offset of its value in the brick
   int gdir[2];       //   across face 3h + k / 16 (that face; 6 for k >= 48)
@@ -395,6 +433,8 @@ __device__ __forceinline__ LaneC<V, CL> lane_consts() {
   for (int a = 0; a < 3; ++a)
     L.foff[a] = uint32_t(a * 16 + dev_face_index(m, a)) * uint32_t(sizeof(CL));
   L.colour = (dev_cx(m) + dev_cy(m) + dev_cz(m)) & 1;
+#pragma unroll
+  for (int d = 0; d < 6; ++d) L.esrc[d] = (L.out[d] ? 8 * (1 + d) : 0) + (L.p[d] >> 3);
   if constexpr (sizeof(V) == 8) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -456,6 +496,7 @@ template <class V, class CL, class CI, int CP = kCpolDefault>
 struct LevelView {
   __amdgpu_buffer_rsrc_t u, b, us, cl, ci, pf;
   const BrickMeta *meta;
+  const ParentNbrs *pnb;
   uint32_t nlb;
   V iscale;
 };
@@ -471,6 +512,7 @@ __device__ __forceinline__ LevelView<V, CL, CI, CP> level_view(const LevelArgs<V
   X.ci = make_rsrc(A.cf.inner, (nb - nlb) * 256 * sizeof(CI));
   X.pf = make_rsrc(A.pf, nb * 48 * sizeof(CL));
   X.meta = A.T.meta;
+  X.pnb = A.T.pnb;
   X.nlb = A.T.nlb;
   X.iscale = A.cf.iscale;
   return X;
@@ -585,32 +627,130 @@ __device__ __forceinline__ void face_values_gathered(__amdgpu_buffer_rsrc_t x,
   }
 }
 
+// The FAS correction u_P - u*_P of the parent cell of the lane's cell
+// (Algorithm 4, prolongation): the brick covers octant o of its parent
+// brick, whose cells o * 8 .. o * 8 + 7 are the parents of its 2^3 blocks.
 template <class V, class CL, class CI, int CP>
+__device__ __forceinline__ V own_correction(const LevelView<V, CL, CI, CP> &X,
+                                            const LaneC<V, CL> &L, const BrickMeta &M) {
+  uint32_t base = uint32_t(M.parent) * 64u + uint32_t(octant_of(M)) * 8u;
+  uint32_t q = L.m >> 3;
+  return bload<V>(X.u, q, base) - bload<V>(X.us, q, base - X.nlb * 64u);
+}
+
+// Prolongation folded into the first post-smoothing half-sweep of a level.
+// Algorithm 4 adds u_P - u*_P to every active cell of the level before the
+// post-smoothing; a colour-c half-sweep reads only the colour-c cells' own
+// values and their neighbours, so it can add the corrections to what it
+// reads instead, and store the corrected colour-c cells it updates.  The
+// other colour's cells are left uncorrected in memory: the next half-sweep
+// overwrites the active ones without reading their old values, except in
+// the T-junction ghosts, where it adds the correction itself (mode 2 of
+// smooth_brick).  Inactive cells are not corrected (as before); their face
+// coefficients are zero, so a correction added to them changes no sum.
+//
+// The corrections one brick needs lie in at most seven parent octants: its
+// own and those of the bricks across its six faces (octant o ^ (1 << a) of
+// the same parent, or of the parent's neighbour when the face lies on the
+// parent's face; ParentNbrs).  Lane k < 56 fetches entry k & 7 of octant
+// slot k >> 3 (0: the brick's own, 1 + d: across face d) in one load of
+// each vector; a face without a same-level brick beyond it (wall,
+// T-junction) is out of range and gets a zero correction.  Each lane then
+// takes the correction of its own parent cell from lane m >> 3 and that of
+// its neighbour across face d (in the brick or beyond it) from lane
+// L.esrc[d].
+template <class V, class CL, class CI, int CP>
+__device__ __forceinline__ V prolong_gather(const LevelView<V, CL, CI, CP> &X,
+                                            const LaneC<V, CL> &L, const BrickMeta &M,
+                                            const ParentNbrs &PN) {
+  // every brick above the coarsest level has a parent
+  const bool has_parent = M.parent >= 0;
+  const uint32_t P = uint32_t(M.parent);
+  const uint32_t o = uint32_t(octant_of(M));
+  const uint32_t slot = L.m >> 3;
+  uint32_t pb = P, oc = o;
+  bool valid = slot == 0u;
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    const int a = d >> 1;
+    const uint32_t bit = 1u << a;
+    const bool across = ((o & bit) != 0u) == ((d & 1) != 0);
+    const int32_t nb = across ? PN.across[a] : int32_t(P);
+    if (slot == uint32_t(1 + d)) {
+      pb = uint32_t(nb);
+      oc = o ^ bit;
+      valid = M.nbr[d] >= 0 && nb >= 0;
+    }
+  }
+  valid = valid && has_parent;
+  const uint32_t cell = pb * 64u + oc * 8u + (L.m & 7u);
+  const uint32_t ou = valid ? cell * uint32_t(sizeof(V)) : kOutOfRange;
+  const uint32_t os = valid ? (cell - X.nlb * 64u) * uint32_t(sizeof(V)) : kOutOfRange;
+  return bload_bytes<V>(X.u, ou, 0) - bload_bytes<V>(X.us, os, 0);
+}
+
+// T-junction ghosts (Eq. 10) of a brick with T-faces: across each T-face d
+// the lane's value becomes u_m + (u_J - mean of the active siblings) / 2,
+// u_J read from the coarser leaf.  The coarse values of all T-faces are
+// requested before any is used, so a brick with several T-faces waits for
+// one round trip.  PR as in stencil_sum: the own values get the FAS
+// correction first (1: corr from prolong_gather; 2: the not yet stored
+// correction of the colour-`colour` cells).
+template <int PR, class V, class CL, class CI, int CP>
+__device__ __forceinline__ void t_ghosts(const LevelView<V, CL, CI, CP> &X, const LaneC<V, CL> &L,
+                                         const BrickMeta &M, V u, V (&v)[6], V corr,
+                                         int colour) {
+  V uJ[6];
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    uJ[d] = V(0);
+    if ((M.flags >> d) & 1u) {
+      uint32_t J = uint32_t(dev_decode_coarse(M.nbr[d]));
+      const BrickMeta MJ = load_meta(X.meta, J);
+      uJ[d] = bload<V>(X.u, uint32_t(coarse_local(M, int(L.m), d, MJ)), J * 64u);
+    }
+  }
+  uint64_t amask = act_mask(M);
+  bool act = (amask >> L.m) & 1ull;
+  if constexpr (PR == 1) {
+    // every lane takes part in the exchange (a lane exchange in a
+    // conditional would read inactive lanes)
+    const V eo = shfl(corr, int(L.m >> 3));
+    u = act ? u + eo : u;
+  }
+  if constexpr (PR == 2) u = act && L.colour == colour ? u + own_correction(X, L, M) : u;
+  V s = group8_sum(act ? u : V(0));
+  int cnt = __popcll((amask >> (L.m & 56u)) & 0xffull);
+  V ubar = cnt ? s / V(cnt) : V(0);
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    if ((M.flags >> d) & 1u) {
+      V g = u + (uJ[d] - ubar) * V(0.5);
+      v[d] = L.out[d] ? g : v[d];
+    }
+  }
+}
+
+// PR: 0 the plain stencil; 1 the first post-smoothing half-sweep with the
+// prolongation folded in (corr from prolong_gather: every neighbour value
+// gets the correction of its parent cell, the T-junction ghosts use the
+// corrected own and sibling values); 2 the half-sweep after it (the
+// ghosts of the colour-`colour` cells add their own, not yet stored,
+// correction).
+template <int PR = 0, class V, class CL, class CI, int CP>
 __device__ __forceinline__ V stencil_sum(const LevelView<V, CL, CI, CP> &X, const LaneC<V, CL> &L,
                                          uint32_t b, const BrickMeta &M, V u, V k0, V k1,
-                                         V k2, V &diag) {
+                                         V k2, V &diag, V corr = V(0), int colour = 0) {
   V v[6], k[6];
   if constexpr (sizeof(V) == 8)
     face_values_gathered<CP>(X.u, X.pf, L, b, M, u, k0, k1, k2, v, k);
   else
     face_values<CP>(X.u, X.pf, L, b, M, u, k0, k1, k2, v, k);
-  if (M.flags & kFlagT) {
-    uint64_t amask = act_mask(M);
-    bool act = (amask >> L.m) & 1ull;
-    V s = group8_sum(act ? u : V(0));
-    int cnt = __popcll((amask >> (L.m & 56u)) & 0xffull);
-    V ubar = cnt ? s / V(cnt) : V(0);
+  if constexpr (PR == 1) {
 #pragma unroll
-    for (int d = 0; d < 6; ++d) {
-      if ((M.flags >> d) & 1u) {
-        uint32_t J = uint32_t(dev_decode_coarse(M.nbr[d]));
-        const BrickMeta MJ = load_meta(X.meta, J);
-        V uJ = bload<V>(X.u, uint32_t(coarse_local(M, int(L.m), d, MJ)), J * 64u);
-        V g = u + (uJ - ubar) * V(0.5);
-        v[d] = L.out[d] ? g : v[d];
-      }
-    }
+    for (int d = 0; d < 6; ++d) v[d] = v[d] + shfl(corr, L.esrc[d]);
   }
+  if (M.flags & kFlagT) t_ghosts<PR>(X, L, M, u, v, corr, colour);
   diag = ((k[0] + k[1]) + (k[2] + k[3])) + (k[4] + k[5]);
   V acc = V(0);
 #pragma unroll
@@ -620,18 +760,22 @@ __device__ __forceinline__ V stencil_sum(const LevelView<V, CL, CI, CP> &X, cons
 
 // One brick of a colour half-sweep of red-black Gauss-Seidel: on the cells
 // of the colour u_m = (b_m + S_m) / c_m, every read taken before the write
-// (the neighbours of a cell all have the other colour).
-template <bool INNER, class V, class CL, class CI, int CP>
+// (the neighbours of a cell all have the other colour).  PR = 1: the first
+// post-smoothing half-sweep with the prolongation folded in; PR = 2: the
+// one after it (see prolong_gather).
+template <bool INNER, int PR, class V, class CL, class CI, int CP>
 __device__ __forceinline__ void smooth_brick(const LevelView<V, CL, CI, CP> &X, const LaneC<V, CL> &L,
                                              uint32_t b, int colour) {
   const BrickMeta M = load_meta(X.meta, b);
+  V corr = V(0);
+  if constexpr (PR == 1) corr = prolong_gather(X, L, M, load_parent_nbrs(X.pnb, b));
   V k0 = own_coef<INNER>(X, b, 1, L.m);
   V k1 = own_coef<INNER>(X, b, 2, L.m);
   V k2 = own_coef<INNER>(X, b, 3, L.m);
   V u = bload<V>(X.u, L.m, b * 64u);
   V rhs = bload<V, CP>(X.b, L.m, b * 64u);
   V c;
-  V S = stencil_sum(X, L, b, M, u, k0, k1, k2, c);
+  V S = stencil_sum<PR>(X, L, b, M, u, k0, k1, k2, c, corr, colour);
   bool act = (act_mask(M) >> L.m) & 1ull;
   if (act && L.colour == colour) bstore<V>(X.u, L.m, b * 64u, div_by(rhs + S, c));
 }
@@ -690,7 +834,7 @@ __device__ __forceinline__ HalfGather half_gather(const LaneC<V, CL> &L, int col
 
 // One brick of a colour half-sweep with gathered face loads: the values,
 // ghosts and sums of smooth_brick, term for term.
-template <bool INNER, class V, class CL, class CI, int CP>
+template <bool INNER, int PR, class V, class CL, class CI, int CP>
 __device__ __forceinline__ void smooth_brick_gathered(const LevelView<V, CL, CI, CP> &X,
                                                       const LaneC<V, CL> &L, const HalfGather &G,
                                                       uint32_t b, int colour) {
@@ -700,6 +844,9 @@ __device__ __forceinline__ void smooth_brick_gathered(const LevelView<V, CL, CI,
   V k2 = own_coef<INNER>(X, b, 3, L.m);
   V u = bload<V>(X.u, L.m, b * 64u);
   V rhs = bload<V, CP>(X.b, L.m, b * 64u);
+  const bool act = (act_mask(M) >> L.m) & 1ull;
+  V corr = V(0);
+  if constexpr (PR == 1) corr = prolong_gather(X, L, M, load_parent_nbrs(X.pnb, b));
   uint32_t gb = 0u;  // byte offset of the brick across the lane's gather face
 #pragma unroll
   for (int d = 0; d < 6; ++d) {
@@ -716,6 +863,7 @@ __device__ __forceinline__ void smooth_brick_gathered(const LevelView<V, CL, CI,
     V vl = bperm(gv, G.gsrc[d]);
     V vs = bperm(u, G.psrc[d]);
     v[d] = L.out[d] ? vl : vs;
+    if constexpr (PR == 1) v[d] = v[d] + shfl(corr, L.esrc[d]);
     if (d & 1) {
       V kl = V(bperm(pfv, G.pfsrc[a]));
       V ks = bperm(kown, G.psrc[d]);
@@ -724,32 +872,17 @@ __device__ __forceinline__ void smooth_brick_gathered(const LevelView<V, CL, CI,
       k[d] = kown;
     }
   }
-  if (M.flags & kFlagT) {
-    uint64_t amask = act_mask(M);
-    bool act = (amask >> L.m) & 1ull;
-    V s = group8_sum(act ? u : V(0));
-    int cnt = __popcll((amask >> (L.m & 56u)) & 0xffull);
-    V ubar = cnt ? s / V(cnt) : V(0);
-#pragma unroll
-    for (int d = 0; d < 6; ++d) {
-      if ((M.flags >> d) & 1u) {
-        uint32_t J = uint32_t(dev_decode_coarse(M.nbr[d]));
-        const BrickMeta MJ = load_meta(X.meta, J);
-        V uJ = bload<V>(X.u, uint32_t(coarse_local(M, int(L.m), d, MJ)), J * 64u);
-        V g = u + (uJ - ubar) * V(0.5);
-        v[d] = L.out[d] ? g : v[d];
-      }
-    }
-  }
+  if (M.flags & kFlagT) t_ghosts<PR>(X, L, M, u, v, corr, colour);
   V c = ((k[0] + k[1]) + (k[2] + k[3])) + (k[4] + k[5]);
   V S = V(0);
 #pragma unroll
   for (int d = 0; d < 6; ++d) S += k[d] * v[d];
-  bool act = (act_mask(M) >> L.m) & 1ull;
   if (act && L.colour == colour) bstore<V>(X.u, L.m, b * 64u, div_by(rhs + S, c));
 }
 
-template <class V, class CL, class CI, int CP = kCpolDefault>
+// PR: 0 a plain half-sweep, 1 the first post-smoothing half-sweep with the
+// prolongation folded in, 2 the half-sweep after it (smooth_brick).
+template <class V, class CL, class CI, int CP = kCpolDefault, int PR = 0>
 __global__ void __launch_bounds__(kBlock) k_smooth(LevelArgs<V, CL, CI> A, int colour) {
   if (A.done && *A.done) return;
   if constexpr (sizeof(V) == 8) {
@@ -758,16 +891,16 @@ __global__ void __launch_bounds__(kBlock) k_smooth(LevelArgs<V, CL, CI> A, int c
     const LevelView<V, CL, CI, CP> X = level_view<CP>(A);
     const WaveLoop W = wave_loop(A.R.n());
     for (uint32_t i = W.first; i < W.end; i += W.step) {
-      if (i < A.R.n_leaf) smooth_brick_gathered<false>(X, L, G, A.R.leaf_lo + i, colour);
-      else smooth_brick_gathered<true>(X, L, G, A.R.inner_lo + (i - A.R.n_leaf), colour);
+      if (i < A.R.n_leaf) smooth_brick_gathered<false, PR>(X, L, G, A.R.leaf_lo + i, colour);
+      else smooth_brick_gathered<true, PR>(X, L, G, A.R.inner_lo + (i - A.R.n_leaf), colour);
     }
   } else {
     const LaneC<V, CL> L = lane_consts<V, CL>();
     const LevelView<V, CL, CI, CP> X = level_view<CP>(A);
     const WaveLoop W = wave_loop(A.R.n());
     for (uint32_t i = W.first; i < W.end; i += W.step) {
-      if (i < A.R.n_leaf) smooth_brick<false>(X, L, A.R.leaf_lo + i, colour);
-      else smooth_brick<true>(X, L, A.R.inner_lo + (i - A.R.n_leaf), colour);
+      if (i < A.R.n_leaf) smooth_brick<false, PR>(X, L, A.R.leaf_lo + i, colour);
+      else smooth_brick<true, PR>(X, L, A.R.inner_lo + (i - A.R.n_leaf), colour);
     }
   }
 }

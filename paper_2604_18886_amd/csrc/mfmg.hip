@@ -184,6 +184,7 @@ struct mfmg_hierarchy {
   mfmg_mg_params prm{};
   int L = 0, lc = 0;
   DevBuf<BrickMeta> meta;  // topology records with this hierarchy's activity masks
+  DevBuf<ParentNbrs> pnb;  // parent-neighbour table (fused prolongation)
   DevBuf<double> coef64;   // nb * 256 (leaf part = assembled, inner = Algorithm 3)
   DevBuf<float> coef32;    // nlb * 256 (mixed)
   DevBuf<__half> coef16;   // (nb - nlb) * 256 (mixed)
@@ -194,6 +195,7 @@ struct mfmg_hierarchy {
   std::vector<char> stream_lv;  // per level: the cycle's stencils stream their coefficients
   bool stream_composite = false;  // the same for the composite operator
   bool fuse_bottom = false;       // level lc + 1 and the coarsest level in one kernel (k_bottom)
+  bool fuse_prolong = true;       // prolongation folded into the post-smoothing (k_smooth PR)
   // work vectors (device order)
   DevBuf<double> U64, B64, S64;  // FP64 cycle: nb*64, nb*64, (nb-nlb)*64
   DevBuf<float> U32, B32, S32;   // mixed cycle
@@ -429,6 +431,7 @@ static Topo make_topo(const DeviceTopology &D, const BrickMeta *meta) {
   t.nb = D.nb;
   t.meta = meta;
   t.child = D.child.p;
+  t.pnb = nullptr;
   return t;
 }
 
@@ -848,6 +851,10 @@ extern "C" mfmg_status mfmg_build_hierarchy(const mfmg_coeffs *co, const mfmg_mg
     hipLaunchKernelGGL(k_active_mask, dim3(grid_for(nlb)), dim3(kBlock), 0, s,
                        (const double *)h->coef64.p, 0u, uint32_t(nlb), h->meta.p);
     Topo topo = make_topo(D, h->meta.p);
+    h->pnb.alloc(size_t(nb));
+    if (nb > 0)
+      hipLaunchKernelGGL(k_parent_nbrs, dim3(unsigned((nb + kBlock - 1) / kBlock)), dim3(kBlock),
+                         0, s, topo, h->pnb.p);
     for (int l = T.max_level - 1; l >= kMinLevel; --l) {
       const Range &R = D.range[l];
       if (R.n_inner == 0) continue;
@@ -944,6 +951,12 @@ extern "C" mfmg_status mfmg_build_hierarchy(const mfmg_coeffs *co, const mfmg_mg
           if (M.flags & kFlagT) ok = false;
       }
       h->fuse_bottom = ok;
+    }
+    {
+      // MFMG_FUSE_PROLONG=0 (read at each build) keeps the separate
+      // prolongation kernel.
+      const char *e = std::getenv("MFMG_FUSE_PROLONG");
+      h->fuse_prolong = !(e && e[0] == '0');
     }
     *out = h.release();
   } catch (const HipError &e) {
@@ -1061,6 +1074,7 @@ struct Cycle {
     const DeviceTopology &D = *h->co->dt;
     LevelArgs<V, CL, CI> A;
     A.T = make_topo(D, h->meta.p);
+    A.T.pnb = h->pnb.p;
     A.cf.leaf = leafc;
     A.cf.inner = innerc;
     A.cf.tc = nullptr;
@@ -1080,14 +1094,26 @@ struct Cycle {
   }
 
   bool stream(int l) const { return h->stream_lv[size_t(l)]; }
-  void half_sweep(int l, const LevelArgs<V, CL, CI> &A, int colour) const {
+  template <int PR>
+  void half_sweep_pr(int l, const LevelArgs<V, CL, CI> &A, int colour) const {
     dim3 g(stencil_grid<V>(A.R.n()));
     if (stream(l))
-      hipLaunchKernelGGL((k_smooth<V, CL, CI, kCpolStream>), g, dim3(kBlock), 0, s, A, colour);
+      hipLaunchKernelGGL((k_smooth<V, CL, CI, kCpolStream, PR>), g, dim3(kBlock), 0, s, A,
+                         colour);
     else
-      hipLaunchKernelGGL((k_smooth<V, CL, CI>), g, dim3(kBlock), 0, s, A, colour);
+      hipLaunchKernelGGL((k_smooth<V, CL, CI, kCpolDefault, PR>), g, dim3(kBlock), 0, s, A,
+                         colour);
   }
-  void smooth(int l, int first, int nu, bool zero_start = false) const {
+  // pr: 0 a plain half-sweep; 1 and 2 the first two half-sweeps of a
+  // post-smoothing that takes the prolongation with it (k_smooth).
+  void half_sweep(int l, const LevelArgs<V, CL, CI> &A, int colour, int pr = 0) const {
+    if (pr == 1) half_sweep_pr<1>(l, A, colour);
+    else if (pr == 2) half_sweep_pr<2>(l, A, colour);
+    else half_sweep_pr<0>(l, A, colour);
+  }
+  // prolong: the level's FAS correction is still to be added (the first
+  // two half-sweeps fold it in; nu >= 1).
+  void smooth(int l, int first, int nu, bool zero_start = false, bool prolong = false) const {
     auto A = args(l, false);
     if (A.R.n() == 0) return;
     for (int it = 0; it < nu; ++it)
@@ -1101,7 +1127,7 @@ struct Cycle {
           else
             hipLaunchKernelGGL((k_smooth_zero<V, CL, CI>), g, dim3(kBlock), 0, s, A, colour);
         } else {
-          half_sweep(l, A, colour);
+          half_sweep(l, A, colour, prolong && it == 0 ? 1 + c : 0);
         }
       }
   }
@@ -1140,10 +1166,13 @@ struct Cycle {
                            dim3(kBlock), 0, s, C);
       for (int k = 0; k < p.mu; ++k) fas(l - 1);
     }
-    hipLaunchKernelGGL((k_prolong<V, CL, CI>), dim3(stencil_grid<V>(A.R.n())), dim3(kBlock),
-                       0, s,
-                       A);
-    smooth(l, 1, p.nu_post);
+    if (h->fuse_prolong && p.nu_post > 0) {
+      smooth(l, 1, p.nu_post, false, true);
+    } else {
+      hipLaunchKernelGGL((k_prolong<V, CL, CI>), dim3(stencil_grid<V>(A.R.n())), dim3(kBlock),
+                         0, s, A);
+      smooth(l, 1, p.nu_post);
+    }
   }
 
   void run() const {
@@ -1191,6 +1220,7 @@ struct CycleT {
     const DeviceTopology &D = *h->co->dt;
     LevelArgsT<V, CL, CI> A;
     A.T = make_topo(D, h->meta.p);
+    A.T.pnb = h->pnb.p;
     A.cf.leaf = leafc;
     A.cf.inner = innerc;
     A.cf.tc = tc;
@@ -2004,7 +2034,10 @@ double cycle_bytes(const mfmg_hierarchy *h) {
     double c_in = double(D.range[l - 1].n_inner) * 64;        // FAS right-hand side
     double c_coef = c_in * 4.0 * CI;
     lvl += c_in * 3.0 * V + c_coef;
-    lvl += n_all * (2.0 * V + 2.0 * V / 8.0);                 // prolongation
+    // prolongation: the parent values, plus the level's iterate unless the
+    // post-smoothing takes the prolongation with it
+    bool fused = h->fuse_prolong && p.nu_post > 0;
+    lvl += n_all * ((fused ? 0.0 : 2.0 * V) + 2.0 * V / 8.0);
     total += visits * lvl;
   }
   return total;
