@@ -126,9 +126,12 @@ __device__ __forceinline__ V div_by(V a, V c) {
 }
 
 // Coarse cell (local Morton index inside the coarse leaf brick J) seen from
-// cell m of brick M across direction d at a T-junction.
-__device__ __forceinline__ int coarse_local(const BrickMeta &M, int m, int d,
-                                            const BrickMeta &MJ) {
+// cell m of brick M across direction d at a T-junction: the coarse cell
+// holding the fine position next to m, i.e. that position's global
+// coordinates halved.  J's cells start at a multiple of 4 on every axis, so
+// the local index is the halved coordinate modulo 4 and J's own record is
+// not needed.
+__device__ __forceinline__ int coarse_local(const BrickMeta &M, int m, int d) {
   int a = d >> 1;
   int s = (d & 1) ? 1 : -1;
   int loc[3] = {dev_cx(m), dev_cy(m), dev_cz(m)};
@@ -136,7 +139,7 @@ __device__ __forceinline__ int coarse_local(const BrickMeta &M, int m, int d,
 #pragma unroll
   for (int ax = 0; ax < 3; ++ax) {
     int g = M.coord[ax] * 4 + loc[ax] + (ax == a ? s : 0);
-    c[ax] = ((g >> 1) - MJ.coord[ax] * 4) & 3;
+    c[ax] = (g >> 1) & 3;
   }
   return dev_morton(c[0], c[1], c[2]);
 }
@@ -706,8 +709,7 @@ __device__ __forceinline__ void t_ghosts(const LevelView<V, CL, CI, CP> &X, cons
     uJ[d] = V(0);
     if ((M.flags >> d) & 1u) {
       uint32_t J = uint32_t(dev_decode_coarse(M.nbr[d]));
-      const BrickMeta MJ = load_meta(X.meta, J);
-      uJ[d] = bload<V>(X.u, uint32_t(coarse_local(M, int(L.m), d, MJ)), J * 64u);
+      uJ[d] = bload<V>(X.u, uint32_t(coarse_local(M, int(L.m), d)), J * 64u);
     }
   }
   uint64_t amask = act_mask(M);
@@ -774,8 +776,7 @@ __device__ __forceinline__ V stencil_sum(const LevelView<V, CL, CI, CP> &X, cons
       for (int d = 0; d < 6; ++d) {
         if ((M.flags >> d) & 1u) {
           uint32_t J = uint32_t(dev_decode_coarse(M.nbr[d]));
-          const BrickMeta MJ = load_meta(X.meta, J);
-          V uJ = bload<V>(X.u, uint32_t(coarse_local(M, int(L.m), d, MJ)), J * 64u);
+          V uJ = bload<V>(X.u, uint32_t(coarse_local(M, int(L.m), d)), J * 64u);
           V g = u + (uJ - ubar) * V(0.5);
           v[d] = L.out[d] ? g : v[d];
         }

@@ -91,8 +91,7 @@ __device__ __forceinline__ double composite_AuT(const Topo &T, const double *__r
         v = 0.0;
       } else {
         int32_t J = dev_decode_coarse(nb);
-        const BrickMeta MJ = T.meta[J];
-        double uJ = X[uint32_t(J) * 64u + coarse_local(M, m, d, MJ)];
+        double uJ = X[uint32_t(J) * 64u + coarse_local(M, m, d)];
         if (d & 1) k = TC[uint32_t(M.tplus) * 48u + a * 16 + dev_face_index(m, a)];
         acc -= k * u;
         tpart += k * 0.5 * (u - uJ);
