@@ -108,6 +108,13 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint6
 // (non-temporal: the line is a first candidate for eviction from L2).
 constexpr int kCpolDefault = 0;
 constexpr int kCpolStream = 2;
+// Level-kernel policy (not an operand value): the coefficient arrays load
+// non-temporal, the right-hand side and the plus-face table with the
+// default policy.  coef_pol / side_pol give the operand of each kind of
+// load for a level policy (kCpolDefault, kCpolStream or this).
+constexpr int kCpolStreamCoef = 0x100;
+constexpr int coef_pol(int cp) { return cp == kCpolStreamCoef ? kCpolStream : cp; }
+constexpr int side_pol(int cp) { return cp == kCpolStreamCoef ? kCpolDefault : cp; }
 
 // Load of element `lane` of the array at element offset `base` (the lane
 // offset goes to voffset, the uniform base to soffset).

@@ -494,7 +494,10 @@ __device__ __forceinline__ WaveLoop wave_loop(uint32_t n) {
 // arrays, plus-face table, right-hand side).  On a level larger than the
 // Infinity Cache these are loaded non-temporal, so that the iterate -- the
 // only array read again for neighbouring bricks -- keeps the L2; on smaller
-// levels everything stays cached for the next half-sweep.
+// levels everything stays cached for the next half-sweep.  kCpolStreamCoef
+// streams only the coefficients: the FP32 cycle's finest level then keeps
+// its iterate, right-hand side and plus-face table (216 MB on the large
+// workload) in the 256 MB Infinity Cache from one half-sweep to the next.
 template <class V, class CL, class CI, int CP = kCpolDefault>
 struct LevelView {
   __amdgpu_buffer_rsrc_t u, b, us, cl, ci, pf;
@@ -528,11 +531,11 @@ template <bool INNER, class V, class CL, class CI, int CP>
 __device__ __forceinline__ V own_coef(const LevelView<V, CL, CI, CP> &X, uint32_t b, int comp,
                                       uint32_t m) {
   if constexpr (INNER) {
-    V v = V(bload<CI, CP>(X.ci, m, (b - X.nlb) * 256u + uint32_t(comp) * 64u));
+    V v = V(bload<CI, coef_pol(CP)>(X.ci, m, (b - X.nlb) * 256u + uint32_t(comp) * 64u));
     if constexpr (std::is_same<CL, CI>::value) return v;
     else return v * X.iscale;
   } else {
-    return V(bload<CL, CP>(X.cl, m, b * 256u + uint32_t(comp) * 64u));
+    return V(bload<CL, coef_pol(CP)>(X.cl, m, b * 256u + uint32_t(comp) * 64u));
   }
 }
 
@@ -581,7 +584,7 @@ __device__ __forceinline__ void face_values(__amdgpu_buffer_rsrc_t x, __amdgpu_b
     V vs = shfl(u, L.p[d]);
     v[d] = L.out[d] ? vl : vs;
     if (d & 1) {
-      V kl = V(bload_bytes<CL, CP>(pf, L.foff[a], b * uint32_t(48 * sizeof(CL))));
+      V kl = V(bload_bytes<CL, side_pol(CP)>(pf, L.foff[a], b * uint32_t(48 * sizeof(CL))));
       V ks = shfl(kown, L.p[d]);
       k[d] = L.out[d] ? kl : ks;
     } else {
@@ -612,7 +615,7 @@ __device__ __forceinline__ void face_values_gathered(__amdgpu_buffer_rsrc_t x,
   }
   V g0 = bload_bytes<V>(x, L.goff[0] + gb0, 0);
   V g1 = bload_bytes<V>(x, L.goff[1] + gb1, 0);
-  CL pfv = bload_bytes<CL, CP>(pf, L.pfoff, b * uint32_t(48 * sizeof(CL)));
+  CL pfv = bload_bytes<CL, side_pol(CP)>(pf, L.pfoff, b * uint32_t(48 * sizeof(CL)));
 #pragma unroll
   for (int d = 0; d < 6; ++d) {
     int a = d >> 1;
@@ -805,7 +808,7 @@ __device__ __forceinline__ void smooth_brick(const LevelView<V, CL, CI, CP> &X, 
   V k1 = own_coef<INNER>(X, b, 2, L.m);
   V k2 = own_coef<INNER>(X, b, 3, L.m);
   V u = bload<V>(X.u, L.m, b * 64u);
-  V rhs = bload<V, CP>(X.b, L.m, b * 64u);
+  V rhs = bload<V, side_pol(CP)>(X.b, L.m, b * 64u);
   V c;
   V S = stencil_sum<PR>(X, L, b, M, u, k0, k1, k2, c, corr, colour);
   bool act = (act_mask(M) >> L.m) & 1ull;
@@ -875,7 +878,7 @@ __device__ __forceinline__ void smooth_brick_gathered(const LevelView<V, CL, CI,
   V k1 = own_coef<INNER>(X, b, 2, L.m);
   V k2 = own_coef<INNER>(X, b, 3, L.m);
   V u = bload<V>(X.u, L.m, b * 64u);
-  V rhs = bload<V, CP>(X.b, L.m, b * 64u);
+  V rhs = bload<V, side_pol(CP)>(X.b, L.m, b * 64u);
   const bool act = (act_mask(M) >> L.m) & 1ull;
   V corr = V(0);
   if constexpr (PR == 1) corr = prolong_gather(X, L, M, load_parent_nbrs(X.pnb, b));
@@ -886,7 +889,7 @@ __device__ __forceinline__ void smooth_brick_gathered(const LevelView<V, CL, CI,
     gb = G.gdir == d ? sb : gb;
   }
   V gv = bload_bytes<V>(X.u, G.goff + gb, 0);
-  CL pfv = bload_bytes<CL, CP>(X.pf, G.pfoff, b * uint32_t(48 * sizeof(CL)));
+  CL pfv = bload_bytes<CL, side_pol(CP)>(X.pf, G.pfoff, b * uint32_t(48 * sizeof(CL)));
   V v[6], k[6];
 #pragma unroll
   for (int d = 0; d < 6; ++d) {
@@ -952,7 +955,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zero(LevelArgs<V, CL, CI> A, 
     const BrickMeta M = load_meta(X.meta, b);
     bool act = (act_mask(M) >> L.m) & 1ull;
     V c = own_coef<false>(X, b, 0, L.m);
-    V rhs = bload<V, CP>(X.b, L.m, b * 64u);
+    V rhs = bload<V, side_pol(CP)>(X.b, L.m, b * 64u);
     bstore<V>(X.u, L.m, b * 64u, act && L.colour == colour ? div_by(rhs, c) : V(0));
   }
 }
@@ -970,7 +973,7 @@ __device__ __forceinline__ void restrict_brick(const LevelView<V, CL, CI, CP> &X
   V k1 = own_coef<INNER>(X, b, 2, L.m);
   V k2 = own_coef<INNER>(X, b, 3, L.m);
   V u = bload<V>(X.u, L.m, b * 64u);
-  V rhs = bload<V, CP>(X.b, L.m, b * 64u);
+  V rhs = bload<V, side_pol(CP)>(X.b, L.m, b * 64u);
   V c;
   V S = stencil_sum(X, L, b, M, u, k0, k1, k2, c);
   uint64_t amask = act_mask(M);
@@ -1477,7 +1480,7 @@ __device__ __forceinline__ void sweep_w_brick(const LevelViewT<V, CL, CI, CP> &X
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     V kown = own_coef<INNER>(X.c, b, 1 + a, L.m);
-    V kl = V(bload_bytes<CL, CP>(X.c.pf, L.foff[a], b * uint32_t(48 * sizeof(CL))));
+    V kl = V(bload_bytes<CL, side_pol(CP)>(X.c.pf, L.foff[a], b * uint32_t(48 * sizeof(CL))));
     V ks = shfl(kown, L.p[2 * a + 1]);
     kd[2 * a] = kown;
     kd[2 * a + 1] = L.out[2 * a + 1] ? kl : ks;

@@ -121,7 +121,8 @@ inline unsigned stencil_grid_T(int64_t bricks) {
 // right-hand side) and iterate together exceed the 256 MB Infinity Cache
 // gains nothing from caching those streams for the next launch, and they
 // only push the iterate's lines out of L2: such launches load them
-// non-temporal (kCpolStream).  Measured on the large workload: the finest
+// non-temporal (kCpolStream; the FP32 cycle streams only the coefficients,
+// Cycle::kCpolLevel).  Measured on the large workload: the finest
 // mixed half-sweep (about 415 MB) runs 11% faster that way, the next
 // level (about 140 MB, re-read from the Infinity Cache by the following
 // half-sweep) 20% slower.  MFMG_STREAM_BYTES (read once) overrides the
@@ -1066,6 +1067,14 @@ struct Cycle {
   V *U, *B, *Ust;
   const int *done;
   hipStream_t s;
+  // Policy of a streamed level's single-use loads.  FP32 cycle: only the
+  // coefficients stream, so the finest level's iterate, right-hand side and
+  // plus-face table stay in the Infinity Cache between half-sweeps (large
+  // workload: finest half-sweep 114 -> 106 us, cycle 1.82 -> 1.77 ms).
+  // FP64: all of them stream; its finest level's iterate, right-hand side
+  // and plus faces alone exceed the cache, and keeping them cached made the
+  // cycle slower (2.98 -> 3.14 ms).
+  static constexpr int kCpolLevel = sizeof(V) == 4 ? kCpolStreamCoef : kCpolStream;
 
   V iscale(int l) const {
     return std::is_same<CI, __half>::value ? V(std::ldexp(1.0, -l)) : V(1);
@@ -1098,7 +1107,7 @@ struct Cycle {
   void half_sweep_pr(int l, const LevelArgs<V, CL, CI> &A, int colour) const {
     dim3 g(stencil_grid<V>(A.R.n()));
     if (stream(l))
-      hipLaunchKernelGGL((k_smooth<V, CL, CI, kCpolStream, PR>), g, dim3(kBlock), 0, s, A,
+      hipLaunchKernelGGL((k_smooth<V, CL, CI, kCpolLevel, PR>), g, dim3(kBlock), 0, s, A,
                          colour);
     else
       hipLaunchKernelGGL((k_smooth<V, CL, CI, kCpolDefault, PR>), g, dim3(kBlock), 0, s, A,
@@ -1122,7 +1131,7 @@ struct Cycle {
         dim3 g(stencil_grid<V>(A.R.n()));
         if (zero_start && it == 0 && c == 0) {
           if (stream(l))
-            hipLaunchKernelGGL((k_smooth_zero<V, CL, CI, kCpolStream>), g, dim3(kBlock), 0, s,
+            hipLaunchKernelGGL((k_smooth_zero<V, CL, CI, kCpolLevel>), g, dim3(kBlock), 0, s,
                                A, colour);
           else
             hipLaunchKernelGGL((k_smooth_zero<V, CL, CI>), g, dim3(kBlock), 0, s, A, colour);
@@ -1148,7 +1157,7 @@ struct Cycle {
     auto A = args(l, false);
     V scale = V(p.beta_mg / p.alpha);
     if (stream(l))
-      hipLaunchKernelGGL((k_restrict<V, CL, CI, kCpolStream>), dim3(stencil_grid<V>(A.R.n())),
+      hipLaunchKernelGGL((k_restrict<V, CL, CI, kCpolLevel>), dim3(stencil_grid<V>(A.R.n())),
                          dim3(kBlock), 0, s, A, scale);
     else
       hipLaunchKernelGGL((k_restrict<V, CL, CI>), dim3(stencil_grid<V>(A.R.n())), dim3(kBlock),
