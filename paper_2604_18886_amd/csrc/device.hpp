@@ -132,21 +132,18 @@ __device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, uint32_t lane, uint
         T, __builtin_amdgcn_raw_buffer_load_b16(r, int(lane * n), int(base * n), CPOL));
 }
 
-template <class T>
+template <class T, int CPOL = kCpolDefault>
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t lane, uint32_t base,
-                                       T v);
-template <>
-__device__ __forceinline__ void bstore<float>(__amdgpu_buffer_rsrc_t r, uint32_t lane,
-                                              uint32_t base, float v) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, int(lane * 4u),
-                                        int(base * 4u), 0);
-}
-template <>
-__device__ __forceinline__ void bstore<double>(__amdgpu_buffer_rsrc_t r, uint32_t lane,
-                                               uint32_t base, double v) {
-  typedef unsigned u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned))));
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, int(lane * 8u),
-                                        int(base * 8u), 0);
+                                       T v) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "bstore: 4- or 8-byte values");
+  if constexpr (sizeof(T) == 8) {
+    typedef unsigned u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned))));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, int(lane * 8u),
+                                          int(base * 8u), CPOL);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, int(lane * 4u),
+                                          int(base * 4u), CPOL);
+  }
 }
 
 // Scalars of one PCG solve, resident in device memory.

@@ -242,7 +242,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_rz(PcgArgs P, const double *r, c
   const WaveLoop W = wave_loop(P.T.nlb);
   double part = 0.0;
   for (uint32_t b = W.first; b < W.end; b += W.step)
-    part += bload<double>(rr, m, b * 64u) * (double(bload<V>(zr, m, b * 64u)) * zs);
+    part += bload<double, kCpolStream>(rr, m, b * 64u) * (double(bload<V>(zr, m, b * 64u)) * zs);
   block_partial(part, P.partials);
 }
 
@@ -270,7 +270,8 @@ __global__ void __launch_bounds__(kBlock) k_pcg_p(PcgArgs P, const V *z, double 
     double v = double(bload<V>(zr, m, b * 64u)) * zs;
     if (!first) {
       double po = bload<double>(pr, m, b * 64u);
-      bstore<double>(xr, m, b * 64u, bload<double>(xr, m, b * 64u) + alpha * po);
+      bstore<double, kCpolStream>(xr, m, b * 64u,
+                                  bload<double, kCpolStream>(xr, m, b * 64u) + alpha * po);
       v += beta * po;
     }
     bstore<double>(pr, m, b * 64u, v);
@@ -455,15 +456,25 @@ __global__ void __launch_bounds__(kBlock) k_pcg_update(PcgArgs P, double *r, V *
   const double2 *a2 = reinterpret_cast<const double2 *>(Ap);
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n2;
        i += int64_t(gridDim.x) * blockDim.x) {
-    double2 rv = r2[i], av = a2[i];
-    rv.x -= alpha * av.x;
-    rv.y -= alpha * av.y;
-    r2[i] = rv;
+    double2 av = a2[i];
     if (r_low) {
+      // mixed: the cycle reads the FP32 copy next, r only in the next
+      // (r, z), after the whole cycle: r passes the caches non-temporal
+      typedef double d2 __attribute__((ext_vector_type(2)));
+      d2 rv = __builtin_nontemporal_load(reinterpret_cast<d2 *>(r2 + i));
+      rv.x -= alpha * av.x;
+      rv.y -= alpha * av.y;
+      __builtin_nontemporal_store(rv, reinterpret_cast<d2 *>(r2 + i));
       r_low[2 * i] = V(rv.x * sc);
       r_low[2 * i + 1] = V(rv.y * sc);
+      part += rv.x * rv.x + rv.y * rv.y;
+    } else {
+      double2 rv = r2[i];
+      rv.x -= alpha * av.x;
+      rv.y -= alpha * av.y;
+      r2[i] = rv;
+      part += rv.x * rv.x + rv.y * rv.y;
     }
-    part += rv.x * rv.x + rv.y * rv.y;
   }
   if (defer) return;  // the null-space shift completes this step
   block_partial(part, P.partials);
