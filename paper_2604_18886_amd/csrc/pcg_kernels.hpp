@@ -269,7 +269,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_p(PcgArgs P, const V *z, double 
   for (uint32_t b = W.first; b < W.end; b += W.step) {
     double v = double(bload<V>(zr, m, b * 64u)) * zs;
     if (!first) {
-      double po = bload<double>(pr, m, b * 64u);
+      double po = bload<double, kCpolStream>(pr, m, b * 64u);
       bstore<double, kCpolStream>(xr, m, b * 64u,
                                   bload<double, kCpolStream>(xr, m, b * 64u) + alpha * po);
       v += beta * po;
@@ -456,7 +456,8 @@ __global__ void __launch_bounds__(kBlock) k_pcg_update(PcgArgs P, double *r, V *
   const double2 *a2 = reinterpret_cast<const double2 *>(Ap);
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n2;
        i += int64_t(gridDim.x) * blockDim.x) {
-    double2 av = a2[i];
+    typedef double d2a __attribute__((ext_vector_type(2)));
+    d2a av = __builtin_nontemporal_load(reinterpret_cast<const d2a *>(a2 + i));
     if (r_low) {
       // mixed: the cycle reads the FP32 copy next, r only in the next
       // (r, z), after the whole cycle: r passes the caches non-temporal
