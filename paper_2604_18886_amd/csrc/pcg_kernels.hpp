@@ -267,7 +267,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_p(PcgArgs P, const V *z, double 
   const WaveLoop W = wave_loop(P.T.nlb);
   if (!first && blockIdx.x == 0 && threadIdx.x == 0) P.S->xpend = 0;
   for (uint32_t b = W.first; b < W.end; b += W.step) {
-    double v = double(bload<V>(zr, m, b * 64u)) * zs;
+    double v = double(bload<V, kCpolStream>(zr, m, b * 64u)) * zs;
     if (!first) {
       double po = bload<double, kCpolStream>(pr, m, b * 64u);
       bstore<double, kCpolStream>(xr, m, b * 64u,
