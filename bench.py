@@ -88,8 +88,8 @@ def summarize_trace(stats_csv):
     kernels = {}
     with open(stats_csv) as fh:
         for r in csv.DictReader(fh):
-            # "void mfmg::k_smooth<float, float, __half, 2, 0>(mfmg::LevelArgs<...>, int)"
-            # -> "mfmg::k_smooth<float, float, __half, 2, 0>"
+            # "void mfmg::k_smooth<float, float, __half, 256, 0>(mfmg::LevelArgs<...>, int)"
+            # -> "mfmg::k_smooth<float, float, __half, 256, 0>"
             name = r["Name"].strip()
             if name.startswith("void "):
                 name = name[5:]
@@ -641,7 +641,7 @@ def main():
             "kernel": f"k_smooth<float,float,__half> colour half-sweep, level {L}",
             "algorithmic_bytes_per_launch": head["smooth_bytes"],
             "avg_launch_us": head["smooth_ms"] * 1e3,
-            "rocprof_avg_launch_us": traced_launch_us("mfmg::k_smooth<float, float, __half, 2, 0>"),
+            "rocprof_avg_launch_us": traced_launch_us("mfmg::k_smooth<float, float, __half, 256, 0>"),
             "stream_copy_gbs": head["copy_gbs"],
             "frac_of_stream_copy": head["smooth_gbs"] / head["copy_gbs"]}
     cpu = None

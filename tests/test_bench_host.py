@@ -14,7 +14,7 @@ import pytest
 import bench
 
 KIB = 1024.0
-MIXED = "void mfmg::k_smooth<float, float, __half, 2, 0>(mfmg::LevelArgs<float, float, __half>, int)"
+MIXED = "void mfmg::k_smooth<float, float, __half, 256, 0>(mfmg::LevelArgs<float, float, __half>, int)"
 FP64 = "void mfmg::k_smooth<double, double, double, 2, 0>(mfmg::LevelArgs<double, double, double>, int)"
 COPY = "__amd_rocclr_copyBuffer"
 
@@ -139,10 +139,10 @@ def test_trace_summary_keeps_kernel_averages_with_the_source(tmp_path, monkeypat
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "h-current")
     bench.summarize_trace(stats)
-    assert bench.traced_launch_us("mfmg::k_smooth<float, float, __half, 2, 0>") == 110.0
+    assert bench.traced_launch_us("mfmg::k_smooth<float, float, __half, 256, 0>") == 110.0
     assert bench.traced_launch_us("mfmg::k_restrict<float, float, __half, 2>") is None
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "h-edited")
-    assert bench.traced_launch_us("mfmg::k_smooth<float, float, __half, 2, 0>") is None
+    assert bench.traced_launch_us("mfmg::k_smooth<float, float, __half, 256, 0>") is None
 
 
 def test_more_than_one_gpu_is_refused_with_a_message():
