@@ -43,10 +43,11 @@ def log(*a):
 
 
 def kernel_source_hash():
-    """Hash of the sources that define the level kernels (the dominant one
-    and everything it calls)."""
+    """Hash of the sources that define the kernels and their launches (the
+    dominant kernel, everything it calls, the Krylov kernels and the host
+    code that sets grids and cache policies)."""
     h = hashlib.sha256()
-    for f in ("kernels.hpp", "device.hpp"):
+    for f in ("kernels.hpp", "device.hpp", "pcg_kernels.hpp", "mfmg.hip"):
         with open(os.path.join(ROOT, "paper_2604_18886_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

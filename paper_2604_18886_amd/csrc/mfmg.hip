@@ -78,13 +78,14 @@ inline unsigned grid_for(int64_t bricks) {
 }
 // Grid of the level kernels (wave_loop): a multiple of 8 workgroups, at
 // most waves_per_xcd waves per XCD, each looping over its share of bricks.
-// Measured on the finest level of the large workload: the FP32 stencils are
-// fastest with 2048 waves per XCD looping; the FP64 ones (more registers,
-// five waves resident per SIMD) with 1920, three rounds of them (FP64
-// half-sweep 207 -> 192 us against one brick per wave).  Reductions over
-// the leaves keep the 2048 cap, so that one workgroup adds their partials.
-// MFMG_WAVES_PER_XCD (read once) overrides the cap, for tuning.
-constexpr int64_t kWavesPerXcd32 = 2048;
+// Measured on the large workload: the FP32 stencils and the reductions over
+// the leaves are fastest with 3072 waves per XCD looping (mixed solve 42.35
+// -> 41.62 ms against 2048; 4096 and 6144 gave 41.85 ms); the FP64
+// stencils (more registers, five waves resident per SIMD) with 1920, three
+// rounds of them (FP64 half-sweep 207 -> 192 us against one brick per
+// wave).  One workgroup of k_finish adds the reductions' partials, however
+// many.  MFMG_WAVES_PER_XCD (read once) overrides the cap, for tuning.
+constexpr int64_t kWavesPerXcd32 = 3072;
 constexpr int64_t kWavesPerXcd64 = 1920;
 inline int64_t waves_override() {
   static const int64_t v = [] {
@@ -111,11 +112,13 @@ inline unsigned stencil_grid(int64_t bricks) {
 }
 // The transposed cycle's stencils (adjoint solves) keep one brick per wave
 // in FP64: they do not use the gathered face loads, and looping made them
-// slower.
+// slower.  In FP32 they loop with 2048 waves per XCD (3072 made the mixed
+// adjoint solve slower, 93.8 -> 94.6 ms).
+constexpr int64_t kWavesPerXcdT32 = 2048;
 template <class V>
 inline unsigned stencil_grid_T(int64_t bricks) {
   if (waves_override()) return grid_waves(bricks, waves_override());
-  return grid_waves(bricks, sizeof(V) == 8 ? int64_t(1) << 30 : kWavesPerXcd32);
+  return grid_waves(bricks, sizeof(V) == 8 ? int64_t(1) << 30 : kWavesPerXcdT32);
 }
 // A stencil launch whose single-use streams (coefficients, plus faces,
 // right-hand side) and iterate together exceed the 256 MB Infinity Cache
