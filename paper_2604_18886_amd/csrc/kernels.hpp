@@ -1157,6 +1157,48 @@ __device__ __forceinline__ int32_t unpack_nbr(uint64_t v, int d) {
   return int32_t(int8_t(uint8_t(v >> (8 * d))));
 }
 
+// Fixed part of the stencil of one brick (slot index i of its level) in
+// k_bottom: the six face coefficients as the stencil sees them (own k_a on
+// the minus side, the partner's or the plus-face table's on the plus side),
+// their sum in the stencil's order, and the LDS index of each neighbour
+// value (partner p in this brick or in the neighbouring one; 0xffff at a
+// wall), two 16-bit indices per word.
+template <class V, class CL>
+__device__ __forceinline__ void bottom_faces(const LaneC<V, CL> &L, uint32_t i, uint64_t nbr,
+                                             const V (&kown)[3], const V (&kpl)[3],
+                                             V (&k)[6], V &c, uint32_t (&lds)[3]) {
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    int a = d >> 1;
+    int p = L.p[d];
+    int32_t nl = unpack_nbr(nbr, d);
+    int32_t nbase = L.out[d] ? (nl >= 0 ? nl * 64 : -1) : int32_t(i) * 64;
+    uint32_t idx = nbase >= 0 ? uint32_t(nbase + p) : 0xffffu;
+    if (d & 1) {
+      V ks = shfl(kown[a], p);
+      k[d] = L.out[d] ? kpl[a] : ks;
+      lds[a] |= idx << 16;
+    } else {
+      k[d] = kown[a];
+      lds[a] = idx;
+    }
+  }
+  c = ((k[0] + k[1]) + (k[2] + k[3])) + (k[4] + k[5]);
+}
+
+// Neighbour sum of k_bottom's stencil over an LDS iterate (bottom_faces).
+template <class V>
+__device__ __forceinline__ V bottom_sum(const V *su, const V (&k)[6], const uint32_t (&lds)[3]) {
+  V S = V(0);
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    uint32_t idx = (lds[d >> 1] >> (16 * (d & 1))) & 0xffffu;
+    V v = idx != 0xffffu ? su[idx] : V(0);
+    S += k[d] * v;
+  }
+  return S;
+}
+
 template <class V, class CL, class CI>
 __global__ void __launch_bounds__(1024) k_bottom(LevelArgs<V, CL, CI> Af, LevelArgs<V, CL, CI> Ac,
                                                  int nu_pre, int nu_post, int nu_coarse, int mu,
@@ -1173,8 +1215,12 @@ __global__ void __launch_bounds__(1024) k_bottom(LevelArgs<V, CL, CI> Af, LevelA
   const uint32_t nw = blockDim.x / kWave;
   const uint32_t nf = Af.R.n(), nc = Ac.R.n();
   const uint32_t m = L.m;
-  V rf[kCoarsestSlots], kf[kCoarsestSlots][3], pf[kCoarsestSlots][3];
-  uint64_t nbf[kCoarsestSlots];    // packed local neighbour indices
+  // per slot: right-hand side, the six face coefficients as the stencil
+  // sees them and their sum (the diagonal), and the LDS index of each of the
+  // six neighbour values (two 16-bit indices per word, 0xffff at a wall);
+  // all fixed for the whole kernel, so the half-sweeps only read LDS and add
+  V rf[kCoarsestSlots], kf[kCoarsestSlots][6], cf[kCoarsestSlots];
+  uint32_t lf[kCoarsestSlots][3];
   uint64_t af[kCoarsestSlots];
   uint32_t parf[kCoarsestSlots];  // 64 x (parent's local index) + 8 x octant
 #pragma unroll
@@ -1185,11 +1231,12 @@ __global__ void __launch_bounds__(1024) k_bottom(LevelArgs<V, CL, CI> Af, LevelA
     uint32_t b = Af.R.brick(i);
     const BrickMeta M = load_meta(Xf.meta, b);
     af[j] = act_mask(M);
+    V kown[3], kpl[3];
     for (int a = 0; a < 3; ++a) {
-      kf[j][a] = inner ? own_coef<true>(Xf, b, 1 + a, m) : own_coef<false>(Xf, b, 1 + a, m);
-      pf[j][a] = V(bload_bytes<CL>(Xf.pf, L.foff[a], b * uint32_t(48 * sizeof(CL))));
+      kown[a] = inner ? own_coef<true>(Xf, b, 1 + a, m) : own_coef<false>(Xf, b, 1 + a, m);
+      kpl[a] = V(bload_bytes<CL>(Xf.pf, L.foff[a], b * uint32_t(48 * sizeof(CL))));
     }
-    nbf[j] = pack_nbr(M, Af.R, Xf.nlb);
+    bottom_faces(L, i, pack_nbr(M, Af.R, Xf.nlb), kown, kpl, kf[j], cf[j], lf[j]);
     parf[j] = (Ac.R.n_leaf + uint32_t(M.parent) - Ac.R.inner_lo) * 64u +
               uint32_t(octant_of(M)) * 8u;
     rf[j] = bload<V>(Xf.b, m, b * 64u);
@@ -1198,8 +1245,8 @@ __global__ void __launch_bounds__(1024) k_bottom(LevelArgs<V, CL, CI> Af, LevelA
   // the coarsest level: coefficients (loaded now, used after the
   // restriction); its leaf bricks keep their iterate and right-hand side
   V rc = V(0);
-  V kc[3], pc[3];
-  uint64_t nbc = 0;
+  V kc[6], cc = V(0);
+  uint32_t lc[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu};
   uint64_t ac = 0;
   bool cin = false;
   if (w < nc) {
@@ -1207,11 +1254,12 @@ __global__ void __launch_bounds__(1024) k_bottom(LevelArgs<V, CL, CI> Af, LevelA
     uint32_t b = Ac.R.brick(w);
     const BrickMeta M = load_meta(Xc.meta, b);
     ac = act_mask(M);
+    V kown[3], kpl[3];
     for (int a = 0; a < 3; ++a) {
-      kc[a] = cin ? own_coef<true>(Xc, b, 1 + a, m) : own_coef<false>(Xc, b, 1 + a, m);
-      pc[a] = V(bload_bytes<CL>(Xc.pf, L.foff[a], b * uint32_t(48 * sizeof(CL))));
+      kown[a] = cin ? own_coef<true>(Xc, b, 1 + a, m) : own_coef<false>(Xc, b, 1 + a, m);
+      kpl[a] = V(bload_bytes<CL>(Xc.pf, L.foff[a], b * uint32_t(48 * sizeof(CL))));
     }
-    nbc = pack_nbr(M, Ac.R, Xc.nlb);
+    bottom_faces(L, w, pack_nbr(M, Ac.R, Xc.nlb), kown, kpl, kc, cc, lc);
     if (!cin) {
       rc = bload<V>(Xc.b, m, b * 64u);
       uc[w * 64u + m] = bload<V>(Xc.u, m, b * 64u);
@@ -1221,26 +1269,9 @@ __global__ void __launch_bounds__(1024) k_bottom(LevelArgs<V, CL, CI> Af, LevelA
 
   // neighbour sum and diagonal of slot j of level f from the LDS iterate
   auto stencil_f = [&](int j, uint32_t i, V &c) {
-    V v[6], k[6];
-#pragma unroll
-    for (int d = 0; d < 6; ++d) {
-      int a = d >> 1;
-      int p = L.p[d];
-      int32_t nl = unpack_nbr(nbf[j], d);
-      int32_t nbase = L.out[d] ? (nl >= 0 ? nl * 64 : -1) : int32_t(i) * 64;
-      v[d] = nbase >= 0 ? uf[nbase + p] : V(0);
-      if (d & 1) {
-        V ks = shfl(kf[j][a], p);
-        k[d] = L.out[d] ? pf[j][a] : ks;
-      } else {
-        k[d] = kf[j][a];
-      }
-    }
-    c = ((k[0] + k[1]) + (k[2] + k[3])) + (k[4] + k[5]);
-    V S = V(0);
-#pragma unroll
-    for (int d = 0; d < 6; ++d) S += k[d] * v[d];
-    return S;
+    (void)i;
+    c = cf[j];
+    return bottom_sum(uf, kf[j], lf[j]);
   };
   auto half_sweep_f = [&](int colour) {
 #pragma unroll
@@ -1299,26 +1330,8 @@ __global__ void __launch_bounds__(1024) k_bottom(LevelArgs<V, CL, CI> Af, LevelA
 
   // the coarsest level: FAS right-hand side, mu solves
   auto stencil_c = [&](V &c) {
-    V v[6], k[6];
-#pragma unroll
-    for (int d = 0; d < 6; ++d) {
-      int a = d >> 1;
-      int p = L.p[d];
-      int32_t nl = unpack_nbr(nbc, d);
-      int32_t nbase = L.out[d] ? (nl >= 0 ? nl * 64 : -1) : int32_t(w) * 64;
-      v[d] = nbase >= 0 ? uc[nbase + p] : V(0);
-      if (d & 1) {
-        V ks = shfl(kc[a], p);
-        k[d] = L.out[d] ? pc[a] : ks;
-      } else {
-        k[d] = kc[a];
-      }
-    }
-    c = ((k[0] + k[1]) + (k[2] + k[3])) + (k[4] + k[5]);
-    V S = V(0);
-#pragma unroll
-    for (int d = 0; d < 6; ++d) S += k[d] * v[d];
-    return S;
+    c = cc;
+    return bottom_sum(uc, kc, lc);
   };
   if (w < nc && cin) {
     V c;
