@@ -23,25 +23,27 @@ def case(request):
     return CASES[request.param]()
 
 
-def _hierarchy(case, fused, **kw):
-    old = os.environ.get("MFMG_FUSE_PROLONG")
+def _hierarchy(case, fused, bottom=True, **kw):
+    saved = {k: os.environ.get(k) for k in ("MFMG_FUSE_PROLONG", "MFMG_FUSE_BOTTOM")}
     os.environ["MFMG_FUSE_PROLONG"] = "1" if fused else "0"
+    os.environ["MFMG_FUSE_BOTTOM"] = "1" if bottom else "0"
     try:
         return case.gpu_hierarchy(**kw)
     finally:
-        if old is None:
-            del os.environ["MFMG_FUSE_PROLONG"]
-        else:
-            os.environ["MFMG_FUSE_PROLONG"] = old
+        for k, v in saved.items():
+            if v is None:
+                del os.environ[k]
+            else:
+                os.environ[k] = v
 
 
-def _outputs(case, seed, **kw):
+def _outputs(case, seed, bottom=True, **kw):
     from paper_2604_18886_amd import mfmg
     rng = np.random.default_rng(seed)
     r = np.where(case.disc.active, rng.uniform(-1, 1, case.T.n), 0.0)
     z = []
     for fused in (True, False):
-        h = _hierarchy(case, fused, **kw)
+        h = _hierarchy(case, fused, bottom, **kw)
         z.append(mfmg.apply_precond(h, case.device(r)).cpu().numpy())
     return z
 
@@ -69,3 +71,12 @@ def test_fused_prolongation_smoothing_counts(case, params):
     z = _outputs(case, 96, precision=0, **params)
     assert np.abs(z[0]).max() > 0.0
     assert rel(z[0], z[1]) <= 1e-13
+
+
+@pytest.mark.parametrize("precision,mu", [(0, 1), (1, 2)])
+def test_fused_prolongation_without_the_fused_bottom(case, precision, mu):
+    """With the bottom of the cycle in separate kernels the level above the
+    coarsest also takes its prolongation in its post-smoothing."""
+    z = _outputs(case, 98, bottom=False, precision=precision, mu=mu)
+    assert np.abs(z[0]).max() > 0.0
+    assert rel(z[0], z[1]) <= (1e-13 if precision == 0 else 1e-6)
