@@ -84,8 +84,15 @@ inline unsigned grid_for(int64_t bricks) {
 // stencils (more registers, five waves resident per SIMD) with 1920, three
 // rounds of them (FP64 half-sweep 207 -> 192 us against one brick per
 // wave).  One workgroup of k_finish adds the reductions' partials, however
-// many.  MFMG_WAVES_PER_XCD (read once) overrides the cap, for tuning.
+// many.  Levels of fewer than 65536 bricks (the small workloads' leaf
+// levels, every coarse level) take 2048 waves per XCD in FP32, so that each
+// wave gets four or more bricks rather than two or three (leaf half-sweep of
+// the 2.3 M-leaf cut-sphere workload 11.7 -> 10.8 us, its mixed solve 6.92
+// -> 6.72 ms; the large workload's mixed solve 41.52 -> 41.48 ms).
+// MFMG_WAVES_PER_XCD (read once) overrides the cap, for tuning.
 constexpr int64_t kWavesPerXcd32 = 3072;
+constexpr int64_t kWavesPerXcdSmall32 = 2048;
+constexpr int64_t kSmallLevelBricks = 65536;
 constexpr int64_t kWavesPerXcd64 = 1920;
 inline int64_t waves_override() {
   static const int64_t v = [] {
@@ -100,15 +107,18 @@ inline unsigned grid_waves(int64_t bricks, int64_t cap) {
   int64_t waves = std::min<int64_t>(std::max<int64_t>(chunk, 1), cap);
   return unsigned(8 * ((waves + kWavesPerBlock - 1) / kWavesPerBlock));
 }
+inline int64_t cap32(int64_t bricks) {
+  return bricks < kSmallLevelBricks ? kWavesPerXcdSmall32 : kWavesPerXcd32;
+}
 // reductions and FP32 stencils
 inline unsigned level_grid(int64_t bricks) {
-  return grid_waves(bricks, waves_override() ? waves_override() : kWavesPerXcd32);
+  return grid_waves(bricks, waves_override() ? waves_override() : cap32(bricks));
 }
 // stencils on values of type V
 template <class V>
 inline unsigned stencil_grid(int64_t bricks) {
   if (waves_override()) return grid_waves(bricks, waves_override());
-  return grid_waves(bricks, sizeof(V) == 8 ? kWavesPerXcd64 : kWavesPerXcd32);
+  return grid_waves(bricks, sizeof(V) == 8 ? kWavesPerXcd64 : cap32(bricks));
 }
 // The transposed cycle's stencils (adjoint solves) keep one brick per wave
 // in FP64: they do not use the gathered face loads, and looping made them
