@@ -1136,8 +1136,13 @@ __global__ void __launch_bounds__(1024) k_coarsest(LevelArgs<V, CL, CI> A, int n
 // the dozen launches of a few microseconds each that the separate kernels
 // take become one.  Every value read and the order of every sum are those
 // of k_fas_rhs, k_smooth, k_restrict, k_coarsest and k_prolong, and the
-// arrays in memory end as those kernels leave them.  fas = 0 skips the FAS
-// right-hand side (a W-cycle's second visit: it is already in B).
+// arrays in memory end as those kernels leave them.  MULTI: the kernel
+// takes `visits` consecutive FAS steps of level f (the level above's mu),
+// both iterates staying in LDS from one to the next; otherwise one step per
+// launch.  fas = 0 skips the FAS right-hand side of the first step (a
+// W-cycle's later visits: it is already in B).  The FP64 cycle takes one
+// step per launch: with the loop its registers spill further (120 against
+// 88 bytes per lane) and the W-cycle got slower.
 constexpr int kBottomCoarse = 1024 / kWave;
 
 // Six local neighbour indices in [-1, 63] packed as bytes (-1: wall).
@@ -1199,10 +1204,10 @@ __device__ __forceinline__ V bottom_sum(const V *su, const V (&k)[6], const uint
   return S;
 }
 
-template <class V, class CL, class CI>
+template <class V, class CL, class CI, bool MULTI>
 __global__ void __launch_bounds__(1024) k_bottom(LevelArgs<V, CL, CI> Af, LevelArgs<V, CL, CI> Ac,
                                                  int nu_pre, int nu_post, int nu_coarse, int mu,
-                                                 int fas, V scale) {
+                                                 int fas, int visits, V scale) {
   if (Af.done && *Af.done) return;
   __shared__ V uf[kCoarsestBricks * 64];  // iterate of level f
   __shared__ V uc[kBottomCoarse * 64];    // iterate of the coarsest level
@@ -1286,88 +1291,90 @@ __global__ void __launch_bounds__(1024) k_bottom(LevelArgs<V, CL, CI> Af, LevelA
     __syncthreads();
   };
 
-  // FAS right-hand side of the inner bricks: b += A u*
-  if (fas) {
-#pragma unroll
-    for (int j = 0; j < kCoarsestSlots; ++j) {
-      uint32_t i = w + uint32_t(j) * nw;
-      if (i >= nf || i < Af.R.n_leaf) continue;
-      V c;
-      V S = stencil_f(j, i, c);
-      V u = uf[i * 64u + m];
-      bool act = (af[j] >> m) & 1ull;
-      rf[j] = act ? rf[j] + (c * u - S) : V(0);
-      bstore<V>(Xf.b, m, Af.R.brick(i) * 64u, rf[j]);
-    }
-    __syncthreads();  // every wave's reads of uf before the first writes
-  }
-  for (int it = 0; it < nu_pre; ++it) {
-    half_sweep_f(0);
-    half_sweep_f(1);
-  }
-  // residual restriction and u* to the coarsest level
-#pragma unroll
-  for (int j = 0; j < kCoarsestSlots; ++j) {
-    uint32_t i = w + uint32_t(j) * nw;
-    if (i >= nf) continue;
-    V c;
-    V S = stencil_f(j, i, c);
-    V u = uf[i * 64u + m];
-    bool act = (af[j] >> m) & 1ull;
-    V r = act ? rf[j] - (c * u - S) : V(0);
-    V rs = group8_sum(r);
-    V us = group8_sum(act ? u : V(0));
-    int cnt = __popcll((af[j] >> (m & 56u)) & 0xffull);
-    if ((m & 7u) == 0) {
-      uint32_t q = parf[j] + (m >> 3);
-      V ust = cnt ? div_by(us, V(cnt)) : V(0);
-      bc[q] = rs * scale;
-      uc[q] = ust;
-      sc[q] = ust;
-    }
-  }
-  __syncthreads();
-
-  // the coarsest level: FAS right-hand side, mu solves
   auto stencil_c = [&](V &c) {
     c = cc;
     return bottom_sum(uc, kc, lc);
   };
-  if (w < nc && cin) {
-    V c;
-    V S = stencil_c(c);
-    V u = uc[w * 64u + m];
-    bool act = (ac >> m) & 1ull;
-    rc = act ? bc[w * 64u + m] + (c * u - S) : V(0);
-  }
-  __syncthreads();
-  int half = nu_coarse / 2;
-  for (int rep = 0; rep < mu; ++rep)
-    for (int it = 0; it < nu_coarse; ++it)
-      for (int h2 = 0; h2 < 2; ++h2) {
-        int colour = it < half ? h2 : 1 - h2;
-        if (w < nc) {
-          V c;
-          V S = stencil_c(c);
-          bool act = (ac >> m) & 1ull;
-          if (act && L.colour == colour) uc[w * 64u + m] = div_by(rc + S, c);
-        }
-        __syncthreads();
-      }
-
-  // prolongation of the correction, post-smoothing
+  for (int visit = 0; visit < (MULTI ? visits : 1); ++visit) {
+    // FAS right-hand side of the inner bricks: b += A u*
+    if (visit == 0 && fas) {
 #pragma unroll
-  for (int j = 0; j < kCoarsestSlots; ++j) {
-    uint32_t i = w + uint32_t(j) * nw;
-    if (i >= nf) continue;
-    uint32_t q = parf[j] + (m >> 3);
-    V corr = uc[q] - sc[q];
-    if ((af[j] >> m) & 1ull) uf[i * 64u + m] = uf[i * 64u + m] + corr;
-  }
-  __syncthreads();
-  for (int it = 0; it < nu_post; ++it) {
-    half_sweep_f(1);
-    half_sweep_f(0);
+      for (int j = 0; j < kCoarsestSlots; ++j) {
+        uint32_t i = w + uint32_t(j) * nw;
+        if (i >= nf || i < Af.R.n_leaf) continue;
+        V c;
+        V S = stencil_f(j, i, c);
+        V u = uf[i * 64u + m];
+        bool act = (af[j] >> m) & 1ull;
+        rf[j] = act ? rf[j] + (c * u - S) : V(0);
+        bstore<V>(Xf.b, m, Af.R.brick(i) * 64u, rf[j]);
+      }
+      __syncthreads();  // every wave's reads of uf before the first writes
+    }
+    for (int it = 0; it < nu_pre; ++it) {
+      half_sweep_f(0);
+      half_sweep_f(1);
+    }
+    // residual restriction and u* to the coarsest level
+#pragma unroll
+    for (int j = 0; j < kCoarsestSlots; ++j) {
+      uint32_t i = w + uint32_t(j) * nw;
+      if (i >= nf) continue;
+      V c;
+      V S = stencil_f(j, i, c);
+      V u = uf[i * 64u + m];
+      bool act = (af[j] >> m) & 1ull;
+      V r = act ? rf[j] - (c * u - S) : V(0);
+      V rs = group8_sum(r);
+      V us = group8_sum(act ? u : V(0));
+      int cnt = __popcll((af[j] >> (m & 56u)) & 0xffull);
+      if ((m & 7u) == 0) {
+        uint32_t q = parf[j] + (m >> 3);
+        V ust = cnt ? div_by(us, V(cnt)) : V(0);
+        bc[q] = rs * scale;
+        uc[q] = ust;
+        sc[q] = ust;
+      }
+    }
+    __syncthreads();
+
+    // the coarsest level: FAS right-hand side, mu solves
+    if (w < nc && cin) {
+      V c;
+      V S = stencil_c(c);
+      V u = uc[w * 64u + m];
+      bool act = (ac >> m) & 1ull;
+      rc = act ? bc[w * 64u + m] + (c * u - S) : V(0);
+    }
+    __syncthreads();
+    int half = nu_coarse / 2;
+    for (int rep = 0; rep < mu; ++rep)
+      for (int it = 0; it < nu_coarse; ++it)
+        for (int h2 = 0; h2 < 2; ++h2) {
+          int colour = it < half ? h2 : 1 - h2;
+          if (w < nc) {
+            V c;
+            V S = stencil_c(c);
+            bool act = (ac >> m) & 1ull;
+            if (act && L.colour == colour) uc[w * 64u + m] = div_by(rc + S, c);
+          }
+          __syncthreads();
+        }
+
+    // prolongation of the correction, post-smoothing
+#pragma unroll
+    for (int j = 0; j < kCoarsestSlots; ++j) {
+      uint32_t i = w + uint32_t(j) * nw;
+      if (i >= nf) continue;
+      uint32_t q = parf[j] + (m >> 3);
+      V corr = uc[q] - sc[q];
+      if ((af[j] >> m) & 1ull) uf[i * 64u + m] = uf[i * 64u + m] + corr;
+    }
+    __syncthreads();
+    for (int it = 0; it < nu_post; ++it) {
+      half_sweep_f(1);
+      half_sweep_f(0);
+    }
   }
 
   // the arrays as the separate kernels leave them

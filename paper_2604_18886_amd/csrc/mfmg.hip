@@ -1178,9 +1178,13 @@ struct Cycle {
     if (l - 1 == h->lc + 1 && h->fuse_bottom) {
       auto F = args(l - 1, false);
       auto Cc = args(h->lc, false);
-      for (int k = 0; k < p.mu; ++k)
-        hipLaunchKernelGGL((k_bottom<V, CL, CI>), dim3(1), dim3(1024), 0, s, F, Cc, p.nu_pre,
-                           p.nu_post, p.nu_coarse, p.mu, int(k == 0), scale);
+      if constexpr (sizeof(V) == 4)
+        hipLaunchKernelGGL((k_bottom<V, CL, CI, true>), dim3(1), dim3(1024), 0, s, F, Cc,
+                           p.nu_pre, p.nu_post, p.nu_coarse, p.mu, 1, p.mu, scale);
+      else
+        for (int k = 0; k < p.mu; ++k)
+          hipLaunchKernelGGL((k_bottom<V, CL, CI, false>), dim3(1), dim3(1024), 0, s, F, Cc,
+                             p.nu_pre, p.nu_post, p.nu_coarse, p.mu, int(k == 0), 1, scale);
     } else {
       auto C = args(l - 1, true);
       if (C.R.n())
