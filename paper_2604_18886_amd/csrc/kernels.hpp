@@ -1166,19 +1166,21 @@ __device__ __forceinline__ int32_t unpack_nbr(uint64_t v, int d) {
 // k_bottom: the six face coefficients as the stencil sees them (own k_a on
 // the minus side, the partner's or the plus-face table's on the plus side),
 // their sum in the stencil's order, and the LDS index of each neighbour
-// value (partner p in this brick or in the neighbouring one; 0xffff at a
-// wall), two 16-bit indices per word.
+// value (partner p in this brick or in the neighbouring one; at a wall the
+// index `zero`: an LDS entry that holds 0, or kBottomWall), two 16-bit
+// indices per word.
 template <class V, class CL>
 __device__ __forceinline__ void bottom_faces(const LaneC<V, CL> &L, uint32_t i, uint64_t nbr,
                                              const V (&kown)[3], const V (&kpl)[3],
-                                             V (&k)[6], V &c, uint32_t (&lds)[3]) {
+                                             uint32_t zero, V (&k)[6], V &c,
+                                             uint32_t (&lds)[3]) {
 #pragma unroll
   for (int d = 0; d < 6; ++d) {
     int a = d >> 1;
     int p = L.p[d];
     int32_t nl = unpack_nbr(nbr, d);
     int32_t nbase = L.out[d] ? (nl >= 0 ? nl * 64 : -1) : int32_t(i) * 64;
-    uint32_t idx = nbase >= 0 ? uint32_t(nbase + p) : 0xffffu;
+    uint32_t idx = nbase >= 0 ? uint32_t(nbase + p) : zero;
     if (d & 1) {
       V ks = shfl(kown[a], p);
       k[d] = L.out[d] ? kpl[a] : ks;
@@ -1192,16 +1194,52 @@ __device__ __forceinline__ void bottom_faces(const LaneC<V, CL> &L, uint32_t i, 
 }
 
 // Neighbour sum of k_bottom's stencil over an LDS iterate (bottom_faces).
+// FP64: a wall reads the zero entry, so the six reads take no branch (mixed
+// W-cycle of the large workload, FP64: 9.98 -> 9.69 ms); FP32: a wall's
+// index is kBottomWall and its read is skipped (reading the zero entry made
+// the FP32 half-sweeps slower: W-cycle 6.24 -> 6.34 ms).  The sums are the
+// same either way.
+constexpr uint32_t kBottomWall = 0xffffu;
 template <class V>
 __device__ __forceinline__ V bottom_sum(const V *su, const V (&k)[6], const uint32_t (&lds)[3]) {
   V S = V(0);
 #pragma unroll
   for (int d = 0; d < 6; ++d) {
     uint32_t idx = (lds[d >> 1] >> (16 * (d & 1))) & 0xffffu;
-    V v = idx != 0xffffu ? su[idx] : V(0);
+    V v;
+    if constexpr (sizeof(V) == 8) v = su[idx];
+    else v = idx != kBottomWall ? su[idx] : V(0);
     S += k[d] * v;
   }
   return S;
+}
+
+// k_bottom's set-up loads of a brick's own face coefficients (axes 1-3),
+// raw: the store that does not hold the brick is addressed out of range and
+// reads 0, so the loads of all slots issue without a branch between them.
+template <class V, class CL, class CI, int CP>
+__device__ __forceinline__ void own_coef_raw(const LevelView<V, CL, CI, CP> &X, uint32_t b,
+                                             bool inner, uint32_t m, CI (&ri)[3],
+                                             CL (&rl)[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    uint32_t comp = uint32_t(1 + a);
+    uint32_t oi = inner ? ((b - X.nlb) * 256u + comp * 64u) * uint32_t(sizeof(CI)) : kOutOfRange;
+    uint32_t ol = inner ? kOutOfRange : (b * 256u + comp * 64u) * uint32_t(sizeof(CL));
+    ri[a] = bload_bytes<CI, coef_pol(CP)>(X.ci, m * uint32_t(sizeof(CI)), oi);
+    rl[a] = bload_bytes<CL, coef_pol(CP)>(X.cl, m * uint32_t(sizeof(CL)), ol);
+  }
+}
+// The coefficient own_coef gives, from own_coef_raw's values.
+template <class V, class CL, class CI, int CP>
+__device__ __forceinline__ V own_coef_of(const LevelView<V, CL, CI, CP> &X, bool inner, CI ri,
+                                         CL rl) {
+  if (inner) {
+    V v = V(ri);
+    if constexpr (std::is_same<CL, CI>::value) return v;
+    else return v * X.iscale;
+  }
+  return V(rl);
 }
 
 template <class V, class CL, class CI, bool MULTI>
@@ -1209,8 +1247,13 @@ __global__ void __launch_bounds__(1024) k_bottom(LevelArgs<V, CL, CI> Af, LevelA
                                                  int nu_pre, int nu_post, int nu_coarse, int mu,
                                                  int fas, int visits, V scale) {
   if (Af.done && *Af.done) return;
-  __shared__ V uf[kCoarsestBricks * 64];  // iterate of level f
-  __shared__ V uc[kBottomCoarse * 64];    // iterate of the coarsest level
+  // the iterates of level f and of the coarsest level, each with a zero
+  // entry after it that FP64's wall reads take (bottom_sum)
+  constexpr uint32_t kZf = kCoarsestBricks * 64, kZc = kBottomCoarse * 64;
+  constexpr uint32_t kWf = sizeof(V) == 8 ? kZf : kBottomWall;
+  constexpr uint32_t kWc = sizeof(V) == 8 ? kZc : kBottomWall;
+  __shared__ V uf[kZf + 1];
+  __shared__ V uc[kZc + 1];
   __shared__ V bc[kBottomCoarse * 64];    // restricted residual of its inner cells
   __shared__ V sc[kBottomCoarse * 64];    // u* of its inner cells
   const LaneC<V, CL> L = lane_consts<V, CL>();
@@ -1220,32 +1263,78 @@ __global__ void __launch_bounds__(1024) k_bottom(LevelArgs<V, CL, CI> Af, LevelA
   const uint32_t nw = blockDim.x / kWave;
   const uint32_t nf = Af.R.n(), nc = Ac.R.n();
   const uint32_t m = L.m;
+  // FP32: the set-up issues every slot's loads before it uses any (set-up
+  // of a V-cycle's launch 12.2 -> 8.5 us; before, each inner coefficient
+  // load waited in a branch of its own), and the half-sweeps read every
+  // slot's neighbours before any slot writes.  FP64 goes slot by slot: the
+  // values held would add to its register spills.
+  constexpr bool kBatch = sizeof(V) == 4;
+  if (threadIdx.x == 0) {
+    uf[kZf] = V(0);
+    uc[kZc] = V(0);
+  }
   // per slot: right-hand side, the six face coefficients as the stencil
   // sees them and their sum (the diagonal), and the LDS index of each of the
-  // six neighbour values (two 16-bit indices per word, 0xffff at a wall);
-  // all fixed for the whole kernel, so the half-sweeps only read LDS and add
+  // six neighbour values (two 16-bit indices per word); all fixed for the
+  // whole kernel, so the half-sweeps only read LDS and add
   V rf[kCoarsestSlots], kf[kCoarsestSlots][6], cf[kCoarsestSlots];
   uint32_t lf[kCoarsestSlots][3];
   uint64_t af[kCoarsestSlots];
   uint32_t parf[kCoarsestSlots];  // 64 x (parent's local index) + 8 x octant
+  if constexpr (kBatch) {
+    CI ri[kCoarsestSlots][3];
+    CL rl[kCoarsestSlots][3], rp[kCoarsestSlots][3];
+    V ru[kCoarsestSlots];
 #pragma unroll
-  for (int j = 0; j < kCoarsestSlots; ++j) {
-    uint32_t i = w + uint32_t(j) * nw;
-    if (i >= nf) continue;
-    bool inner = i >= Af.R.n_leaf;
-    uint32_t b = Af.R.brick(i);
-    const BrickMeta M = load_meta(Xf.meta, b);
-    af[j] = act_mask(M);
-    V kown[3], kpl[3];
-    for (int a = 0; a < 3; ++a) {
-      kown[a] = inner ? own_coef<true>(Xf, b, 1 + a, m) : own_coef<false>(Xf, b, 1 + a, m);
-      kpl[a] = V(bload_bytes<CL>(Xf.pf, L.foff[a], b * uint32_t(48 * sizeof(CL))));
+    for (int j = 0; j < kCoarsestSlots; ++j) {
+      uint32_t i = w + uint32_t(j) * nw;
+      if (i >= nf) continue;
+      uint32_t b = Af.R.brick(i);
+      own_coef_raw(Xf, b, i >= Af.R.n_leaf, m, ri[j], rl[j]);
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        rp[j][a] = bload_bytes<CL>(Xf.pf, L.foff[a], b * uint32_t(48 * sizeof(CL)));
+      rf[j] = bload<V>(Xf.b, m, b * 64u);
+      ru[j] = bload<V>(Xf.u, m, b * 64u);
     }
-    bottom_faces(L, i, pack_nbr(M, Af.R, Xf.nlb), kown, kpl, kf[j], cf[j], lf[j]);
-    parf[j] = (Ac.R.n_leaf + uint32_t(M.parent) - Ac.R.inner_lo) * 64u +
-              uint32_t(octant_of(M)) * 8u;
-    rf[j] = bload<V>(Xf.b, m, b * 64u);
-    uf[i * 64u + m] = bload<V>(Xf.u, m, b * 64u);
+#pragma unroll
+    for (int j = 0; j < kCoarsestSlots; ++j) {
+      uint32_t i = w + uint32_t(j) * nw;
+      if (i >= nf) continue;
+      bool inner = i >= Af.R.n_leaf;
+      const BrickMeta M = load_meta(Xf.meta, Af.R.brick(i));
+      af[j] = act_mask(M);
+      V kown[3], kpl[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        kown[a] = own_coef_of(Xf, inner, ri[j][a], rl[j][a]);
+        kpl[a] = V(rp[j][a]);
+      }
+      bottom_faces(L, i, pack_nbr(M, Af.R, Xf.nlb), kown, kpl, kWf, kf[j], cf[j], lf[j]);
+      parf[j] = (Ac.R.n_leaf + uint32_t(M.parent) - Ac.R.inner_lo) * 64u +
+                uint32_t(octant_of(M)) * 8u;
+      uf[i * 64u + m] = ru[j];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < kCoarsestSlots; ++j) {
+      uint32_t i = w + uint32_t(j) * nw;
+      if (i >= nf) continue;
+      bool inner = i >= Af.R.n_leaf;
+      uint32_t b = Af.R.brick(i);
+      const BrickMeta M = load_meta(Xf.meta, b);
+      af[j] = act_mask(M);
+      V kown[3], kpl[3];
+      for (int a = 0; a < 3; ++a) {
+        kown[a] = inner ? own_coef<true>(Xf, b, 1 + a, m) : own_coef<false>(Xf, b, 1 + a, m);
+        kpl[a] = V(bload_bytes<CL>(Xf.pf, L.foff[a], b * uint32_t(48 * sizeof(CL))));
+      }
+      bottom_faces(L, i, pack_nbr(M, Af.R, Xf.nlb), kown, kpl, kWf, kf[j], cf[j], lf[j]);
+      parf[j] = (Ac.R.n_leaf + uint32_t(M.parent) - Ac.R.inner_lo) * 64u +
+                uint32_t(octant_of(M)) * 8u;
+      rf[j] = bload<V>(Xf.b, m, b * 64u);
+      uf[i * 64u + m] = bload<V>(Xf.u, m, b * 64u);
+    }
   }
   // the coarsest level: coefficients (loaded now, used after the
   // restriction); its leaf bricks keep their iterate and right-hand side
@@ -1264,7 +1353,7 @@ __global__ void __launch_bounds__(1024) k_bottom(LevelArgs<V, CL, CI> Af, LevelA
       kown[a] = cin ? own_coef<true>(Xc, b, 1 + a, m) : own_coef<false>(Xc, b, 1 + a, m);
       kpl[a] = V(bload_bytes<CL>(Xc.pf, L.foff[a], b * uint32_t(48 * sizeof(CL))));
     }
-    bottom_faces(L, w, pack_nbr(M, Ac.R, Xc.nlb), kown, kpl, kc, cc, lc);
+    bottom_faces(L, w, pack_nbr(M, Ac.R, Xc.nlb), kown, kpl, kWc, kc, cc, lc);
     if (!cin) {
       rc = bload<V>(Xc.b, m, b * 64u);
       uc[w * 64u + m] = bload<V>(Xc.u, m, b * 64u);
@@ -1278,15 +1367,34 @@ __global__ void __launch_bounds__(1024) k_bottom(LevelArgs<V, CL, CI> Af, LevelA
     c = cf[j];
     return bottom_sum(uf, kf[j], lf[j]);
   };
+  // (FP32: every slot's neighbour sum is read before any slot writes: a
+  // cell of the colour reads only cells of the other colour, which no lane
+  // writes in this half-sweep; the other lanes' sums are not used.)
   auto half_sweep_f = [&](int colour) {
+    if constexpr (kBatch) {
+      V S[kCoarsestSlots];
 #pragma unroll
-    for (int j = 0; j < kCoarsestSlots; ++j) {
-      uint32_t i = w + uint32_t(j) * nw;
-      if (i >= nf) continue;
-      V c;
-      V S = stencil_f(j, i, c);
-      bool act = (af[j] >> m) & 1ull;
-      if (act && L.colour == colour) uf[i * 64u + m] = div_by(rf[j] + S, c);
+      for (int j = 0; j < kCoarsestSlots; ++j) {
+        uint32_t i = w + uint32_t(j) * nw;
+        if (i < nf) S[j] = bottom_sum(uf, kf[j], lf[j]);
+      }
+#pragma unroll
+      for (int j = 0; j < kCoarsestSlots; ++j) {
+        uint32_t i = w + uint32_t(j) * nw;
+        if (i >= nf) continue;
+        bool act = (af[j] >> m) & 1ull;
+        if (act && L.colour == colour) uf[i * 64u + m] = div_by(rf[j] + S[j], cf[j]);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < kCoarsestSlots; ++j) {
+        uint32_t i = w + uint32_t(j) * nw;
+        if (i >= nf) continue;
+        V c;
+        V S = stencil_f(j, i, c);
+        bool act = (af[j] >> m) & 1ull;
+        if (act && L.colour == colour) uf[i * 64u + m] = div_by(rf[j] + S, c);
+      }
     }
     __syncthreads();
   };
@@ -1361,14 +1469,31 @@ __global__ void __launch_bounds__(1024) k_bottom(LevelArgs<V, CL, CI> Af, LevelA
           __syncthreads();
         }
 
-    // prolongation of the correction, post-smoothing
+    // prolongation of the correction (FP32: every slot's reads before the
+    // writes), post-smoothing
+    if constexpr (kBatch) {
+      V un[kCoarsestSlots];
 #pragma unroll
-    for (int j = 0; j < kCoarsestSlots; ++j) {
-      uint32_t i = w + uint32_t(j) * nw;
-      if (i >= nf) continue;
-      uint32_t q = parf[j] + (m >> 3);
-      V corr = uc[q] - sc[q];
-      if ((af[j] >> m) & 1ull) uf[i * 64u + m] = uf[i * 64u + m] + corr;
+      for (int j = 0; j < kCoarsestSlots; ++j) {
+        uint32_t i = w + uint32_t(j) * nw;
+        if (i >= nf) continue;
+        uint32_t q = parf[j] + (m >> 3);
+        un[j] = uf[i * 64u + m] + (uc[q] - sc[q]);
+      }
+#pragma unroll
+      for (int j = 0; j < kCoarsestSlots; ++j) {
+        uint32_t i = w + uint32_t(j) * nw;
+        if (i < nf && ((af[j] >> m) & 1ull)) uf[i * 64u + m] = un[j];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < kCoarsestSlots; ++j) {
+        uint32_t i = w + uint32_t(j) * nw;
+        if (i >= nf) continue;
+        uint32_t q = parf[j] + (m >> 3);
+        V corr = uc[q] - sc[q];
+        if ((af[j] >> m) & 1ull) uf[i * 64u + m] = uf[i * 64u + m] + corr;
+      }
     }
     __syncthreads();
     for (int it = 0; it < nu_post; ++it) {
