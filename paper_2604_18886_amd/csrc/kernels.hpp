@@ -1026,6 +1026,46 @@ __global__ void __launch_bounds__(kBlock) k_fas_rhs(LevelArgs<V, CL, CI> A) {
   }
 }
 
+// The first pre-smoothing half-sweep of a level with the FAS right-hand
+// side folded in, for a level with no leaf at or below it (all its bricks
+// are inner, none has a T-face).  Right after the restriction u = u* on
+// every cell, so one neighbour sum S of u* gives both b += c u* - S (stored
+// on every cell, as k_fas_rhs) and, on the cells of the colour,
+// u = (b + S) / c (as k_smooth).  The sum is read from the u* array, which
+// this launch does not write, so no brick's sum can see another brick's
+// update; values and sums are those of k_fas_rhs and k_smooth.  A
+// neighbour that is not an inner brick (none, on such a level) would read
+// as a wall.
+template <class V, class CL, class CI, int CP = kCpolDefault>
+__global__ void __launch_bounds__(kBlock) k_smooth_fas(LevelArgs<V, CL, CI> A, int colour) {
+  if (A.done && *A.done) return;
+  const LaneC<V, CL> L = lane_consts<V, CL>();
+  const LevelView<V, CL, CI, CP> X = level_view<CP>(A);
+  LevelView<V, CL, CI, CP> Xs = X;  // u = u*, indexed by brick id - nlb
+  Xs.u = X.us;
+  const WaveLoop W = wave_loop(A.R.n_inner);
+  for (uint32_t i = W.first; i < W.end; i += W.step) {
+    uint32_t b = A.R.inner_lo + i;
+    const BrickMeta M = load_meta(X.meta, b);
+    BrickMeta Ms = M;
+#pragma unroll
+    for (int d = 0; d < 6; ++d)
+      Ms.nbr[d] = M.nbr[d] >= int32_t(X.nlb) ? M.nbr[d] - int32_t(X.nlb) : -1;
+    Ms.flags = M.flags & ~uint32_t(kFlagT);
+    V k0 = own_coef<true>(X, b, 1, L.m);
+    V k1 = own_coef<true>(X, b, 2, L.m);
+    V k2 = own_coef<true>(X, b, 3, L.m);
+    V u = bload<V>(X.us, L.m, (b - X.nlb) * 64u);
+    V rhs = bload<V, side_pol(CP)>(X.b, L.m, b * 64u);
+    V c;
+    V S = stencil_sum(Xs, L, b, Ms, u, k0, k1, k2, c);
+    bool act = (act_mask(M) >> L.m) & 1ull;
+    V rf = act ? rhs + (c * u - S) : V(0);
+    bstore<V>(X.b, L.m, b * 64u, rf);
+    if (act && L.colour == colour) bstore<V>(X.u, L.m, b * 64u, div_by(rf + S, c));
+  }
+}
+
 // Prolongation of the FAS correction: u += u_P - u*_P on active cells.
 template <class V, class CL, class CI>
 __global__ void __launch_bounds__(kBlock) k_prolong(LevelArgs<V, CL, CI> A) {

@@ -210,6 +210,7 @@ struct mfmg_hierarchy {
   bool stream_composite = false;  // the same for the composite operator
   bool fuse_bottom = false;       // level lc + 1 and the coarsest level in one kernel (k_bottom)
   bool fuse_prolong = true;       // prolongation folded into the post-smoothing (k_smooth PR)
+  std::vector<char> fold_fas;     // per level: FAS right-hand side folded into k_smooth_fas
   // work vectors (device order)
   DevBuf<double> U64, B64, S64;  // FP64 cycle: nb*64, nb*64, (nb-nlb)*64
   DevBuf<float> U32, B32, S32;   // mixed cycle
@@ -972,6 +973,20 @@ extern "C" mfmg_status mfmg_build_hierarchy(const mfmg_coeffs *co, const mfmg_mg
       const char *e = std::getenv("MFMG_FUSE_PROLONG");
       h->fuse_prolong = !(e && e[0] == '0');
     }
+    {
+      // A level above the coarsest with no leaf at or below it takes its FAS
+      // right-hand side in its first pre-smoothing half-sweep (k_smooth_fas).
+      // MFMG_FUSE_FAS=0 (read at each build) keeps k_fas_rhs.
+      const char *e = std::getenv("MFMG_FUSE_FAS");
+      bool on = !(e && e[0] == '0');
+      h->fold_fas.assign(D.range.size(), 0);
+      bool leaf_below = false;
+      for (size_t l = 0; l < D.range.size(); ++l) {
+        leaf_below = leaf_below || D.range[l].n_leaf > 0;
+        h->fold_fas[l] = on && int(l) > h->lc && int(l) < h->L && !leaf_below &&
+                         D.range[l].n_inner > 0;
+      }
+    }
     *out = h.release();
   } catch (const HipError &e) {
     return hip_fail(e);
@@ -1135,7 +1150,10 @@ struct Cycle {
   }
   // prolong: the level's FAS correction is still to be added (the first
   // two half-sweeps fold it in; nu >= 1).
-  void smooth(int l, int first, int nu, bool zero_start = false, bool prolong = false) const {
+  // fold: the level's FAS right-hand side is still to be formed, by its
+  // first half-sweep (k_smooth_fas; the level has no leaves, nu >= 1).
+  void smooth(int l, int first, int nu, bool zero_start = false, bool prolong = false,
+              bool fold = false) const {
     auto A = args(l, false);
     if (A.R.n() == 0) return;
     for (int it = 0; it < nu; ++it)
@@ -1148,6 +1166,13 @@ struct Cycle {
                                A, colour);
           else
             hipLaunchKernelGGL((k_smooth_zero<V, CL, CI>), g, dim3(kBlock), 0, s, A, colour);
+        } else if (fold && it == 0 && c == 0) {
+          dim3 gi(stencil_grid<V>(A.R.n_inner));
+          if (stream(l))
+            hipLaunchKernelGGL((k_smooth_fas<V, CL, CI, kCpolLevel>), gi, dim3(kBlock), 0, s,
+                               A, colour);
+          else
+            hipLaunchKernelGGL((k_smooth_fas<V, CL, CI>), gi, dim3(kBlock), 0, s, A, colour);
         } else {
           half_sweep(l, A, colour, prolong && it == 0 ? 1 + c : 0);
         }
@@ -1157,7 +1182,8 @@ struct Cycle {
   // zero_start: the level's iterate is zero and its bricks are all leaves
   // (the finest level at the start of a cycle), so the first half-sweep
   // needs no neighbour values and also clears the iterate.
-  void fas(int l, bool zero_start = false) const {
+  // fold: as for smooth (the first visit of a level of fold_fas).
+  void fas(int l, bool zero_start = false, bool fold = false) const {
     const mfmg_mg_params &p = h->prm;
     if (l == h->lc) {
       auto A = args(l, false);
@@ -1166,7 +1192,7 @@ struct Cycle {
                          p.nu_coarse);
       return;
     }
-    smooth(l, 0, p.nu_pre, zero_start);
+    smooth(l, 0, p.nu_pre, zero_start, false, fold);
     auto A = args(l, false);
     V scale = V(p.beta_mg / p.alpha);
     if (stream(l))
@@ -1187,10 +1213,11 @@ struct Cycle {
                              p.nu_pre, p.nu_post, p.nu_coarse, p.mu, int(k == 0), 1, scale);
     } else {
       auto C = args(l - 1, true);
-      if (C.R.n())
+      bool fold = h->fold_fas[size_t(l - 1)] && p.nu_pre > 0;
+      if (C.R.n() && !fold)
         hipLaunchKernelGGL((k_fas_rhs<V, CL, CI>), dim3(stencil_grid<V>(C.R.n_inner)),
                            dim3(kBlock), 0, s, C);
-      for (int k = 0; k < p.mu; ++k) fas(l - 1);
+      for (int k = 0; k < p.mu; ++k) fas(l - 1, false, fold && k == 0);
     }
     if (h->fuse_prolong && p.nu_post > 0) {
       smooth(l, 1, p.nu_post, false, true);
@@ -2059,7 +2086,10 @@ double cycle_bytes(const mfmg_hierarchy *h) {
     lvl += n_all * (2.0 * V + 3.0 * V / 8.0) + cells_coef;  // residual + restriction
     double c_in = double(D.range[l - 1].n_inner) * 64;        // FAS right-hand side
     double c_coef = c_in * 4.0 * CI;
-    lvl += c_in * 3.0 * V + c_coef;
+    // (folded into the first half-sweep of level l - 1: only its store of b)
+    bool fold = l - 1 > h->lc && h->fold_fas[size_t(l - 1)] && p.nu_pre > 0 &&
+                !(l - 1 == h->lc + 1 && h->fuse_bottom);
+    lvl += fold ? c_in * V : c_in * 3.0 * V + c_coef;
     // prolongation: the parent values, plus the level's iterate unless the
     // post-smoothing takes the prolongation with it
     bool fused = h->fuse_prolong && p.nu_post > 0;
